@@ -1,0 +1,165 @@
+/*
+ * tqr -- tiled QR factorisation on one AMD MI355X (gfx950).
+ *
+ * The method is the tiled QR of Buttari, Langou, Kurzak and Dongarra,
+ * "Parallel Tiled QR Factorization for Multicore Architectures":
+ * the matrix is cut into b x b tiles (Sec. 3.1), factorised by four tile
+ * kernels -- GEQRT (their DGEQT2), LARFB (DLARFB), TSQRT (DTSQT2) and
+ * SSRFB (DSSRFB) -- in the order of Algorithm 1, and the tasks are run out of
+ * order as their dependencies allow, highest priority first (Sec. 3.3).
+ * Here one persistent GPU kernel runs that task graph: dependency counters
+ * and priority-ordered ready queues live in device memory.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Every matrix, T array and workspace pointer is DEVICE memory owned by
+ *    the caller.  The library never allocates or frees device memory in a
+ *    call; the workspace size comes from tqr_workspace_bytes().
+ *  - Matrices are column-major with a leading dimension (lda >= max(1,m)).
+ *  - Tile size b (tile_b) and inner block ib (inner_ib): supported pairs are
+ *    b in {16, 32, 64, 128, 256} and ib in {16, 32, 64} with ib <= b,
+ *    b % ib == 0 and ib * (b + ib) <= 9216 (the panel of a tile kernel is
+ *    staged on chip).  ib == b is the paper's unblocked tile kernel with a
+ *    b x b T (Sec. 3.1); ib < b applies each tile's reflectors in blocks of ib.
+ *  - m >= n is required (the paper assumes q <= p, Sec. 3.2; least squares
+ *    needs it).  m == 0 or n == 0 returns TQR_OK at once.
+ *  - Sizes that are not multiples of b are handled by zero-padded edge tiles:
+ *    padded rows give reflector entries that are exactly zero and padded
+ *    columns give tau = 0, so the m x n result is unchanged.
+ *  - Argument errors are reported synchronously, before anything is
+ *    enqueued: the return value is -i when the i-th argument (1-based, in
+ *    signature order) is illegal, as LAPACK's convention; nothing is printed.
+ *    HIP errors return TQR_EDEVICE; tqr_last_error_string() describes the
+ *    last error of the calling thread.
+ *  - All work is enqueued on `stream`; calls return without synchronising.
+ *    Calls on different streams with disjoint buffers are independent.
+ *  - Arithmetic is IEEE FP64; NaN and Inf in the input propagate and are
+ *    not detected.
+ */
+#ifndef TQR_H
+#define TQR_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int tqr_status;
+#define TQR_OK 0
+#define TQR_EDEVICE (-1000)   /* a HIP call failed; see tqr_last_error_string() */
+#define TQR_EABORTED (-1001)  /* device-side abort flag or wait time-out (tqr_factor_ex) */
+
+/* Number of doubles of the T array for an m x n factorisation: p*q slots of
+ * ib x b, p = ceil(m/b), q = ceil(n/b).  Slot (i,k) (0-based tile indices)
+ * starts at element ((k*p) + i) * ib * b and holds, column-major with
+ * leading dimension ib, the ib x ib upper-triangular T of every inner block
+ * s at columns s*ib .. s*ib+ib-1: the compact WY form
+ * H_{s*ib} ... H_{s*ib+ib-1} = I - V_s T_s V_s^T of the block's reflectors
+ * (Sec. 2.1).  Only slots with i >= k are written.  Returns -1 for illegal
+ * sizes. */
+int64_t tqr_t_elems(int64_t m, int64_t n, int tile_b, int inner_ib);
+
+/* Bytes of device workspace needed by tqr_factor (nrhs = 0), tqr_apply_qt /
+ * tqr_apply_q and tqr_solve_ls (nrhs right-hand sides).  Returns -1 for
+ * illegal sizes. */
+int64_t tqr_workspace_bytes(int64_t m, int64_t n, int64_t nrhs, int tile_b, int inner_ib);
+
+/* QR factorisation A = QR by tiles (Sec. 3.1, Algorithm 1).
+ *   m, n     : rows, columns, m >= n >= 0.
+ *   A        : device, m x n column-major, leading dimension lda.  On exit the
+ *              upper triangle of the leading n rows holds R; below it are the
+ *              tiled Householder vectors: V_kk strictly below the diagonal of
+ *              each diagonal tile (unit diagonal implicit) and the full V_ik
+ *              in each tile below (the identity block on top of it is
+ *              implicit, Sec. 3.1).  They are only meaningful together with
+ *              T and the same tile_b / inner_ib; they are not LAPACK's V.
+ *   T        : device, tqr_t_elems() doubles, written (see tqr_t_elems).
+ *   work     : device workspace of at least tqr_workspace_bytes(m,n,0,..)
+ *              bytes; contents on entry are ignored, on exit undefined.
+ *   stream   : HIP stream the work is enqueued on.
+ * Errors: -1 m<0 or m<n, -2 n<0, -3 A null, -4 lda, -5 tile_b, -6 inner_ib,
+ * -7 T null, -8 work null, -9 work_bytes too small. */
+tqr_status tqr_factor(int64_t m, int64_t n, double *A, int64_t lda, int tile_b, int inner_ib,
+                      double *T, void *work, int64_t work_bytes, hipStream_t stream);
+
+/* Execution options for tqr_factor_ex. */
+typedef struct tqr_options {
+    int32_t struct_size;       /* sizeof(tqr_options) */
+    int32_t workgroups;        /* persistent workers; 0 = one per resident slot */
+    int32_t mode;              /* TQR_MODE_PERSISTENT or TQR_MODE_SERIAL */
+    int32_t policy;            /* TQR_POLICY_PAPER (default) or TQR_POLICY_LOOKAHEAD */
+    int64_t *trace;            /* device, 4 int64 per task or NULL: start, end
+                                  (device real-time clock ticks), workgroup, XCD */
+    const volatile int32_t *abort_flag; /* host-mapped or device int polled while
+                                           waiting for work; nonzero aborts; or NULL */
+    int32_t *status;           /* device int or NULL: 0 done, TQR_EABORTED */
+    int64_t timeout_ticks;     /* per-wait bound in device clock ticks; 0 = 10 s */
+} tqr_options;
+
+#define TQR_MODE_PERSISTENT 0  /* one launch; tasks run out of order as the graph allows */
+#define TQR_MODE_SERIAL 1      /* one launch per task, in Algorithm 1 order (reference order) */
+#define TQR_POLICY_PAPER 0     /* ready tasks by kind: GEQRT > TSQRT > LARFB > SSRFB (Sec. 3.3) */
+#define TQR_POLICY_LOOKAHEAD 1 /* as PAPER, but updates of the next panel's tile column first */
+
+/* tqr_factor with explicit execution options (argument errors as
+ * tqr_factor; -11 for a bad options struct). */
+tqr_status tqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, int tile_b, int inner_ib,
+                         double *T, void *work, int64_t work_bytes, hipStream_t stream,
+                         const tqr_options *options);
+
+/* B <- Q^T B with Q from tqr_factor (the DORMQR analogue that the paper's
+ * Sec. 5 names as future work): for k = 0..: LARFB with (V_kk, T_kk) on row
+ * tile k of B, then for i > k the SSRFB form with (V_ik, T_ik) on row tiles
+ * (k, i) -- the factorisation's own transformations in its own order.
+ *   A, T : the output of tqr_factor with the same m, n, tile_b, inner_ib.
+ *   B    : device, m x nrhs column-major, leading dimension ldb, in place.
+ * Errors: -1 m, -2 n, -3 nrhs<0, -4 A null, -5 lda, -6 T null, -7 tile_b,
+ * -8 inner_ib, -9 B null, -10 ldb, -11 work null, -12 work_bytes. */
+tqr_status tqr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                        const double *T, int tile_b, int inner_ib, double *B, int64_t ldb,
+                        void *work, int64_t work_bytes, hipStream_t stream);
+
+/* B <- Q B: the transformations of tqr_apply_qt transposed, in reverse
+ * order.  Q [I_n; 0] is the thin Q.  Arguments and errors as tqr_apply_qt. */
+tqr_status tqr_apply_q(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                       const double *T, int tile_b, int inner_ib, double *B, int64_t ldb,
+                       void *work, int64_t work_bytes, hipStream_t stream);
+
+/* Least squares min ||A X - B||_F for m >= n (the problem of Sec. 2.1 solved
+ * with the tiled factorisation, as LAPACK's dgels does with dgeqrf):
+ * factor A (overwritten as by tqr_factor, T written), B <- Q^T B, then
+ * X = R^{-1} (Q^T B)[0:n] by tiled back substitution; X overwrites
+ * B[0:n, :] and B[n:m, :] holds the residual's coordinates in Q's complement.
+ *   d_info : device int, written 0, or k > 0 when R(k,k) (1-based) is
+ *            exactly zero (then B[0:n,:] is unspecified), as dgels.
+ * Errors: -1 m, -2 n, -3 nrhs, -4 A null, -5 lda, -6 B null, -7 ldb,
+ * -8 tile_b, -9 inner_ib, -10 T null, -11 work null, -12 work_bytes,
+ * -13 d_info null. */
+tqr_status tqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb,
+                        int tile_b, int inner_ib, double *T, void *work, int64_t work_bytes,
+                        int32_t *d_info, hipStream_t stream);
+
+/* Description of the last error returned to the calling host thread. */
+const char *tqr_last_error_string(void);
+
+/* ---- task-graph introspection (host only, no device work) --------------
+ * The persistent scheduler runs a closed-form task graph; these expose it so
+ * that it can be checked against a hazard analysis of Algorithm 1.
+ * Tasks of the factorisation are numbered 0..tqr_graph_tasks()-1.  A task is
+ * (kind, i, j, k, strip): kind 0 GEQRT(k), 1 TSQRT(i,k), 2 LARFB(k,j) on
+ * column strip `strip` of tile (k,j), 3 SSRFB(i,j,k) on column strip
+ * `strip` of tiles (k,j) and (i,j); tile indices 0-based.  Strips are
+ * groups of 64 columns of a tile (one strip when b <= 64). */
+int64_t tqr_graph_tasks(int64_t p, int64_t q, int tile_b);
+int tqr_graph_task(int64_t p, int64_t q, int tile_b, int64_t task, int32_t out[5]);
+int tqr_graph_indegree(int64_t p, int64_t q, int tile_b, int64_t task);
+/* Writes up to max_out successor task ids; returns the successor count. */
+int tqr_graph_successors(int64_t p, int64_t q, int tile_b, int64_t task, int64_t *out, int max_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TQR_H */

@@ -1,0 +1,955 @@
+// tqr: tiled QR (Buttari, Langou, Kurzak, Dongarra) on one MI355X.
+//
+// Layout kernels, the four tile kernels of Sec. 3.1 as workgroup tasks, the
+// persistent task-graph scheduler of Sec. 3.3 and the C entry points of
+// include/tqr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "tqr.h"
+#include "tqr_device.h"
+#include "tqr_graph.h"
+
+namespace tqr {
+
+// ===========================================================================
+// Layout: column-major <-> tiles (Block Data Layout, Sec. 3.4)
+// ===========================================================================
+// Tile (i,j) of a p-row grid of b x tw tiles starts at ((j*p)+i)*b*tw.
+__global__ void k_cm_to_tiles(const double *__restrict__ A, int64_t lda, int64_t m, int64_t n,
+                              double *__restrict__ W, int p, int b, int tw) {
+    const int i = blockIdx.x, j = blockIdx.y;
+    double *t = W + ((int64_t)j * p + i) * b * tw;
+    const int64_t r0 = (int64_t)i * b, c0 = (int64_t)j * tw;
+    for (int idx = threadIdx.x; idx < b * tw; idx += blockDim.x) {
+        const int r = idx % b, c = idx / b;
+        const int64_t gr = r0 + r, gc = c0 + c;
+        t[idx] = (gr < m && gc < n) ? A[gc * lda + gr] : 0.0;
+    }
+}
+
+__global__ void k_tiles_to_cm(const double *__restrict__ W, int p, int b, int tw, double *__restrict__ A,
+                              int64_t lda, int64_t m, int64_t n) {
+    const int i = blockIdx.x, j = blockIdx.y;
+    const double *t = W + ((int64_t)j * p + i) * b * tw;
+    const int64_t r0 = (int64_t)i * b, c0 = (int64_t)j * tw;
+    for (int idx = threadIdx.x; idx < b * tw; idx += blockDim.x) {
+        const int r = idx % b, c = idx / b;
+        const int64_t gr = r0 + r, gc = c0 + c;
+        if (gr < m && gc < n) A[gc * lda + gr] = t[idx];
+    }
+}
+
+// ===========================================================================
+// Scheduler state (in the caller's workspace)
+// ===========================================================================
+struct SchedState {
+    uint32_t head[8];
+    uint32_t tail[8];
+    uint32_t done;
+    int32_t status;
+    uint32_t pad[14];
+};
+static_assert(sizeof(SchedState) == 128, "state layout");
+
+struct Sched {
+    SchedState *st;
+    int32_t *cnt;     // remaining in-degree per task
+    int32_t *queue;   // kLevels arrays of `cap` task ids, -1 = not yet written
+    int64_t cap;      // = number of tasks
+    int64_t ntasks;
+};
+
+__host__ __device__ inline int64_t sched_bytes(int64_t ntasks) {
+    return (int64_t)sizeof(SchedState) + ((ntasks * 4 * (1 + kLevels) + 255) / 256) * 256;
+}
+
+__host__ inline Sched sched_at(void *base, int64_t ntasks) {
+    Sched s;
+    s.st = reinterpret_cast<SchedState *>(base);
+    s.cnt = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(base) + sizeof(SchedState));
+    s.queue = s.cnt + ntasks;
+    s.cap = ntasks;
+    s.ntasks = ntasks;
+    return s;
+}
+
+template <class G>
+__global__ void k_sched_init(G g, Sched s, int policy, int64_t src0, int64_t src1) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < s.ntasks) {
+        s.cnt[t] = g.indegree(g.decode(t));
+        for (int l = 0; l < kLevels; ++l) s.queue[l * s.cap + t] = -1;
+    }
+    if (t == 0) {
+        for (int l = 0; l < 8; ++l) {
+            s.st->head[l] = 0;
+            s.st->tail[l] = 0;
+        }
+        s.st->done = 0;
+        s.st->status = 0;
+    }
+    (void)policy; (void)src0; (void)src1;
+}
+
+template <class G>
+__device__ __host__ inline int level_of(const G &, const Task &, int) { return 0; }
+template <>
+__device__ __host__ inline int level_of<FactorGraph>(const FactorGraph &g, const Task &t, int policy) {
+    return g.level(t, policy);
+}
+template <>
+__device__ __host__ inline int level_of<TrsmGraph>(const TrsmGraph &, const Task &t, int) {
+    return t.kind == 0 ? 0 : 1;
+}
+
+// Pushes the tasks without predecessors.  Runs as its own launch after
+// k_sched_init, so every slot is already cleared.
+template <class G>
+__global__ void k_sched_seed(G g, Sched s, int policy) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s.ntasks) return;
+    const Task task = g.decode(t);
+    if (g.indegree(task) != 0) return;
+    const int lvl = level_of(g, task, policy);
+    const uint32_t pos = __hip_atomic_fetch_add(&s.st->tail[lvl], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&s.queue[lvl * s.cap + pos], (int32_t)t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Scheduler flags are read and written with system-scope atomics: a
+// system-scope access is never served from a possibly stale copy in one
+// XCD's L2, so a flag written on one XCD is seen on every other.
+#define TQR_FLAG_SCOPE __HIP_MEMORY_SCOPE_SYSTEM
+
+__device__ __forceinline__ uint64_t rt_clock() { return wall_clock64(); }
+
+__device__ __forceinline__ void push_task(const Sched &s, int lvl, int64_t t) {
+    const uint32_t pos = __hip_atomic_fetch_add(&s.st->tail[lvl], 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+    __hip_atomic_store(&s.queue[lvl * s.cap + pos], (int32_t)t, __ATOMIC_RELEASE, TQR_FLAG_SCOPE);
+}
+
+__device__ __forceinline__ void set_status(const Sched &s, int32_t v) {
+    __hip_atomic_store(&s.st->status, v, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+}
+
+constexpr uint32_t kMaxSpins = 1u << 26;  // ~ seconds of s_sleep-paced polling
+
+// Highest-priority ready task; -1 if none is ready; -2 if a reserved slot was
+// not published before the deadline (then the status is set to aborted).
+__device__ int32_t try_pop(const Sched &s, uint64_t deadline) {
+    for (int lvl = 0; lvl < kLevels; ++lvl) {
+        uint32_t *hp = &s.st->head[lvl];
+        uint32_t h = __hip_atomic_load(hp, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+        while (h < __hip_atomic_load(&s.st->tail[lvl], __ATOMIC_RELAXED, TQR_FLAG_SCOPE)) {
+            if (__hip_atomic_compare_exchange_strong(hp, &h, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                     TQR_FLAG_SCOPE)) {
+                // the pusher reserves a slot before it publishes the task id,
+                // so the slot may still read -1 for a moment
+                int32_t *slot = &s.queue[lvl * s.cap + h];
+                int32_t v;
+                uint32_t spins = 0;
+                while ((v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, TQR_FLAG_SCOPE)) < 0) {
+                    // two independent bounds: the clock, and an iteration cap
+                    // that ends the wait even if the clock were not advancing
+                    if (rt_clock() > deadline || ++spins > kMaxSpins) {
+                        set_status(s, TQR_EABORTED);
+                        return -2;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                return v;
+            }
+        }
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int xcc_id() {
+    int v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 0xf;
+}
+
+struct RunOpts {
+    int64_t *trace;
+    const volatile int32_t *abort_flag;
+    int64_t timeout;
+    int policy;
+};
+
+// ===========================================================================
+// Tile kernels (bodies run by one workgroup)
+// ===========================================================================
+template <int B, int IB>
+struct TileKernels {
+    static constexpr int NB = B / IB;
+    static constexpr int WCOLS = 16 * NWAVES;              // columns per workgroup pass
+    static constexpr int LDP = IB + B + 1;                  // panel leading dimension
+    static constexpr size_t PANEL_DOUBLES = (size_t)LDP * IB;
+    static constexpr size_t LDS_BYTES = (PANEL_DOUBLES + 2 * IB * IB + 2 * IB + NWAVES) * sizeof(double);
+
+    struct Lds {
+        double *P, *Ts, *G, *tau, *wv, *red;
+        __device__ explicit Lds(double *base) {
+            P = base;
+            Ts = P + PANEL_DOUBLES;
+            G = Ts + IB * IB;
+            tau = G + IB * IB;
+            wv = tau + IB;
+            red = wv + IB;
+        }
+    };
+
+    // DGEQT2 (GEQRT): A_kk <- V_kk, R_kk; T_kk written; Vkk receives V_kk as
+    // a dense unit-lower matrix for the mask-free updates.
+    __device__ static void geqrt(double *Akk, double *Tkk, double *Vkk, double *smem) {
+        Lds L(smem);
+        const int tid = threadIdx.x;
+#pragma unroll 1
+        for (int s = 0; s < NB; ++s) {
+            const int c0 = s * IB, hp = B - c0;
+            for (int idx = tid; idx < hp * IB; idx += NT) {
+                const int r = idx % hp, c = idx / hp;
+                L.P[(size_t)c * LDP + r] = Akk[(size_t)(c0 + c) * B + c0 + r];
+            }
+            __syncthreads();
+            panel_factor<IB>(L.P, hp, LDP, L.tau, L.wv, L.red);
+            panel_t<IB>(L.P, hp, LDP, L.tau, L.Ts, L.G);
+            for (int idx = tid; idx < hp * IB; idx += NT) {
+                const int r = idx % hp, c = idx / hp;
+                Akk[(size_t)(c0 + c) * B + c0 + r] = L.P[(size_t)c * LDP + r];
+            }
+            for (int idx = tid; idx < B * IB; idx += NT) {
+                const int r = idx % B, c = idx / B;
+                const double x = r < c0 + c ? 0.0 : (r == c0 + c ? 1.0 : L.P[(size_t)c * LDP + r - c0]);
+                Vkk[(size_t)(c0 + c) * B + r] = x;
+            }
+            for (int idx = tid; idx < IB * IB; idx += NT) Tkk[(size_t)c0 * IB + idx] = L.Ts[idx];
+            __syncthreads();
+            // trailing columns c0+IB..B-1 of the tile: I - V T^T V^T
+            for (int col0 = c0 + IB + 16 * wave_id(); col0 < B; col0 += WCOLS) {
+                Strip<B> C;
+                strip_load<B>(C, Akk + (size_t)col0 * B, B);
+                ul_block<B, IB, true>(C, Vkk, Tkk, c0);
+                strip_store<B>(C, Akk + (size_t)col0 * B, B, c0 / 16);
+            }
+            __syncthreads();
+        }
+    }
+
+    // DTSQT2 (TSQRT): [R_kk; A_ik] <- R~_kk, V_ik; T_ik written.  Only the
+    // upper triangle of the diagonal tile is read or written.
+    __device__ static void tsqrt(double *Akk, double *Aik, double *Tik, double *smem) {
+        Lds L(smem);
+        const int tid = threadIdx.x;
+        constexpr int hp = IB + B;
+#pragma unroll 1
+        for (int s = 0; s < NB; ++s) {
+            const int c0 = s * IB;
+            for (int idx = tid; idx < IB * IB; idx += NT) {
+                const int r = idx % IB, c = idx / IB;
+                L.P[(size_t)c * LDP + r] = (r <= c) ? Akk[(size_t)(c0 + c) * B + c0 + r] : 0.0;
+            }
+            for (int idx = tid; idx < B * IB; idx += NT) {
+                const int r = idx % B, c = idx / B;
+                L.P[(size_t)c * LDP + IB + r] = Aik[(size_t)(c0 + c) * B + r];
+            }
+            __syncthreads();
+            panel_factor<IB>(L.P, hp, LDP, L.tau, L.wv, L.red);
+            panel_t<IB>(L.P, hp, LDP, L.tau, L.Ts, L.G);
+            for (int idx = tid; idx < IB * IB; idx += NT) {
+                const int r = idx % IB, c = idx / IB;
+                if (r <= c) Akk[(size_t)(c0 + c) * B + c0 + r] = L.P[(size_t)c * LDP + r];
+                Tik[(size_t)c0 * IB + idx] = L.Ts[idx];
+            }
+            for (int idx = tid; idx < B * IB; idx += NT) {
+                const int r = idx % B, c = idx / B;
+                Aik[(size_t)(c0 + c) * B + r] = L.P[(size_t)c * LDP + IB + r];
+            }
+            __syncthreads();
+            for (int col0 = c0 + IB + 16 * wave_id(); col0 < B; col0 += WCOLS) {
+                Strip<B> C;
+                strip_load<B>(C, Aik + (size_t)col0 * B, B);
+                ts_block<B, IB, true>(C, Akk + (size_t)col0 * B, Aik, Tik, c0);
+                strip_store<B>(C, Aik + (size_t)col0 * B, B);
+            }
+            __syncthreads();
+        }
+    }
+
+    // DLARFB (LARFB) on columns [cbeg, cend) of a b-row tile C with the
+    // reflectors of diagonal tile (V_kk as a dense unit-lower matrix, T_kk):
+    // C <- Q_kk^T C (trans) or Q_kk C.
+    template <bool TRANS>
+    __device__ static void larfb(const double *Akk, const double *Tkk, double *Cb, int cbeg, int cend) {
+        for (int col0 = cbeg + 16 * wave_id(); col0 < cend; col0 += WCOLS) {
+            Strip<B> C;
+            strip_load<B>(C, Cb + (size_t)col0 * B, B);
+#pragma unroll 1
+            for (int s = 0; s < NB; ++s) {
+                const int c0 = (TRANS ? s : NB - 1 - s) * IB;
+                ul_block<B, IB, TRANS>(C, Akk, Tkk, c0);
+            }
+            strip_store<B>(C, Cb + (size_t)col0 * B, B);
+        }
+    }
+
+    // DSSRFB (SSRFB) on columns [cbeg, cend) of the pair (top, C) with the
+    // reflectors (V_ik, T_ik) of a TSQRT tile.
+    template <bool TRANS>
+    __device__ static void ssrfb(double *Top, double *Cb, const double *Vik, const double *Tik, int cbeg, int cend) {
+        for (int col0 = cbeg + 16 * wave_id(); col0 < cend; col0 += WCOLS) {
+            Strip<B> C;
+            strip_load<B>(C, Cb + (size_t)col0 * B, B);
+#pragma unroll 1
+            for (int s = 0; s < NB; ++s) {
+                const int c0 = (TRANS ? s : NB - 1 - s) * IB;
+                ts_block<B, IB, TRANS>(C, Top + (size_t)col0 * B, Vik, Tik, c0);
+            }
+            strip_store<B>(C, Cb + (size_t)col0 * B, B);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Task bodies
+// ---------------------------------------------------------------------------
+template <int B, int IB>
+struct FactorBody {
+    using K = TileKernels<B, IB>;
+    double *W;   // tiles
+    double *T;   // T slots
+    double *Vd;  // dense unit-lower V of each diagonal tile
+    int p;
+    __device__ double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
+    __device__ double *tslot(int i, int k) const { return T + ((int64_t)k * p + i) * IB * B; }
+    __device__ double *vdiag(int k) const { return Vd + (int64_t)k * B * B; }
+    __device__ void run(const Task &t, double *smem) const {
+        const int cbeg = t.c * kStripCols, cend = min(B, cbeg + kStripCols);
+        switch (t.kind) {
+        case GEQRT: K::geqrt(tile(t.k, t.k), tslot(t.k, t.k), vdiag(t.k), smem); break;
+        case TSQRT: K::tsqrt(tile(t.k, t.k), tile(t.i, t.k), tslot(t.i, t.k), smem); break;
+        case LARFB: K::template larfb<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend); break;
+        default:
+            K::template ssrfb<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend);
+            break;
+        }
+    }
+};
+
+// Q^T (TRANS) or Q applied to the p row tiles of B (b x wb each).
+template <int B, int IB, bool TRANS>
+struct ApplyBody {
+    using K = TileKernels<B, IB>;
+    const double *W;
+    const double *T;
+    const double *Vd;  // dense unit-lower V of each diagonal tile
+    double *Bt;
+    int p, wb;
+    __device__ const double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
+    __device__ const double *tslot(int i, int k) const { return T + ((int64_t)k * p + i) * IB * B; }
+    __device__ double *btile(int i) const { return Bt + (int64_t)i * B * wb; }
+    __device__ void run(const Task &t, double *) const {
+        const int cbeg = t.c * kStripCols, cend = min(wb, cbeg + kStripCols);
+        if (t.i == t.k)
+            K::template larfb<TRANS>(Vd + (int64_t)t.k * B * B, tslot(t.k, t.k), btile(t.k), cbeg, cend);
+        else
+            K::template ssrfb<TRANS>(btile(t.k), btile(t.i), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend);
+    }
+};
+
+// Back substitution X = R^{-1} Y with the upper tiles of R; Y/X in the row
+// tiles of B (b x wb).  nrow = n (rows of R that are not padding).
+template <int B>
+struct TrsmBody {
+    const double *W;
+    double *Bt;
+    int p, wb;
+    int64_t nrow;
+    __device__ const double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
+    __device__ double *btile(int i) const { return Bt + (int64_t)i * B * wb; }
+    __device__ void run(const Task &t, double *smem) const {
+        if (t.kind == 1) {
+            // G(i,j): B_i -= R_ij X_j on the matrix cores
+            const double *R = tile(t.i, t.j);
+            const double *X = btile(t.j);
+            double *Y = btile(t.i);
+            const int l = lane_id();
+            for (int col0 = 16 * wave_id(); col0 < wb; col0 += 16 * NWAVES) {
+                Strip<B> C;
+                strip_load<B>(C, Y + (size_t)col0 * B, B);
+                // k-slice (kb, r): rows 16kb + 4r .. +3 of X_j, columns of R
+                const double *xp = X + (size_t)(col0 + (l & 15)) * B + (l >> 4);
+                const double *rp = R + (size_t)(l >> 4) * B + (l & 15);
+#pragma unroll 1
+                for (int kb = 0; kb < B / 16; ++kb) {
+                    const d4 x = -ld4s(xp + 16 * kb, 4);
+                    const double *rk = rp + (size_t)16 * kb * B;
+#pragma unroll
+                    for (int rb = 0; rb < B / 16; ++rb) {
+                        const double *q = rk + 16 * rb;
+                        C.v[rb] = mfma(q[0], x.x, C.v[rb]);
+                        C.v[rb] = mfma(q[4 * B], x.y, C.v[rb]);
+                        C.v[rb] = mfma(q[8 * B], x.z, C.v[rb]);
+                        C.v[rb] = mfma(q[12 * B], x.w, C.v[rb]);
+                    }
+                }
+                strip_store<B>(C, Y + (size_t)col0 * B, B);
+            }
+            return;
+        }
+        // D(i): solve R_ii X_i = Y_i for the rows that are not padding;
+        // padding rows of X_i are set to zero.
+        const double *R = tile(t.i, t.i);
+        double *Y = btile(t.i);
+        const int64_t rem = nrow - (int64_t)t.i * B;
+        const int nloc = (int)(rem < B ? rem : B);
+        const int tid = threadIdx.x;
+        double *y = smem;  // B x 16
+        for (int g0 = 0; g0 < wb; g0 += 16) {
+            for (int idx = tid; idx < B * 16; idx += NT) {
+                const int r = idx % B, c = idx / B;
+                y[idx] = (r < nloc) ? Y[(size_t)(g0 + c) * B + r] : 0.0;
+            }
+            __syncthreads();
+            for (int cidx = nloc - 1; cidx >= 0; --cidx) {
+                const double *rc = R + (size_t)cidx * B;
+                if (tid < 16) y[cidx + tid * B] = y[cidx + tid * B] / rc[cidx];
+                __syncthreads();
+                for (int idx = tid; idx < cidx * 16; idx += NT) {
+                    const int r = idx % cidx, c = idx / cidx;
+                    y[r + c * B] -= rc[r] * y[cidx + c * B];
+                }
+                __syncthreads();
+            }
+            for (int idx = tid; idx < B * 16; idx += NT) {
+                const int r = idx % B, c = idx / B;
+                Y[(size_t)(g0 + c) * B + r] = y[idx];
+            }
+            __syncthreads();
+        }
+    }
+};
+
+// ===========================================================================
+// The persistent scheduler: every workgroup repeatedly takes the
+// highest-priority ready task, runs it, and releases its successors; a
+// successor whose last dependency is released is pushed on its level's queue.
+// ===========================================================================
+template <class G, class Body>
+__global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunOpts o) {
+    extern __shared__ double smem[];
+    __shared__ int32_t s_task;
+    const int tid = threadIdx.x;
+    // One thread-0 region per iteration: it retires the previous task (done
+    // count), then waits for the next.  The task id is made wave-uniform with
+    // readfirstlane, so the loop exit is a scalar branch and every lane of
+    // every wave meets each barrier in the same iteration.
+    bool retire = false;
+    for (;;) {
+        if (tid == 0) {
+            if (retire) __hip_atomic_fetch_add(&s.st->done, 1u, __ATOMIC_RELEASE, TQR_FLAG_SCOPE);
+            int32_t t = -1;
+            const uint64_t deadline = rt_clock() + (uint64_t)o.timeout;
+            uint32_t spins = 0;
+            for (;;) {
+                if (__hip_atomic_load(&s.st->done, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) >= (uint32_t)s.ntasks) break;
+                if (__hip_atomic_load(&s.st->status, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) != 0) break;
+                if (o.abort_flag && __hip_atomic_load(const_cast<int32_t *>(o.abort_flag), __ATOMIC_RELAXED, TQR_FLAG_SCOPE)) {
+                    set_status(s, TQR_EABORTED);
+                    break;
+                }
+                t = try_pop(s, deadline);
+                if (t >= 0) break;
+                if (t == -2 || rt_clock() > deadline || ++spins > kMaxSpins) {
+                    set_status(s, TQR_EABORTED);
+                    t = -1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            s_task = t;
+        }
+        __syncthreads();
+        const int32_t t = __builtin_amdgcn_readfirstlane(s_task);
+        if (t < 0) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const Task task = g.decode(t);
+        if (o.trace && tid == 0) {
+            o.trace[4 * (int64_t)t + 0] = (int64_t)rt_clock();
+            o.trace[4 * (int64_t)t + 2] = blockIdx.x;
+            o.trace[4 * (int64_t)t + 3] = xcc_id();
+        }
+        body.run(task, smem);
+        __threadfence();
+        __syncthreads();
+        if (o.trace && tid == 0) o.trace[4 * (int64_t)t + 1] = (int64_t)rt_clock();
+        const int ns = g.num_successors(task);
+        for (int n = tid; n < ns; n += NT) {
+            const int64_t sidx = g.successor(task, n);
+            const int32_t old = __hip_atomic_fetch_add(&s.cnt[sidx], -1, __ATOMIC_ACQ_REL, TQR_FLAG_SCOPE);
+            if (old == 1) push_task(s, level_of(g, g.decode(sidx), o.policy), sidx);
+        }
+        __syncthreads();
+        retire = true;
+    }
+}
+
+// One task per launch (reference order; no scheduler state).
+template <class G, class Body>
+__global__ void __launch_bounds__(NT) k_one_task(G g, Body body, int64_t t) {
+    extern __shared__ double smem[];
+    body.run(g.decode(t), smem);
+}
+
+__global__ void k_copy_status(const SchedState *st, int32_t *out) { *out = st->status; }
+
+// Dense unit-lower copy of the reflectors of diagonal tile k (block k of the
+// grid): zeros above the diagonal, ones on it, V_kk below.
+__global__ void k_unit_lower(const double *__restrict__ W, int p, int b, double *__restrict__ Vd) {
+    const int k = blockIdx.x;
+    const double *t = W + ((int64_t)k * p + k) * b * b;
+    double *v = Vd + (int64_t)k * b * b;
+    for (int idx = threadIdx.x; idx < b * b; idx += blockDim.x) {
+        const int r = idx % b, c = idx / b;
+        v[idx] = r < c ? 0.0 : (r == c ? 1.0 : t[idx]);
+    }
+}
+
+// d_info: smallest 1-based index k with R(k,k) == 0, else 0.
+__global__ void k_diag_info(const double *W, int p, int b, int64_t n, int32_t *info) {
+    __shared__ int32_t best;
+    if (threadIdx.x == 0) best = 0x7fffffff;
+    __syncthreads();
+    for (int64_t d = threadIdx.x; d < n; d += blockDim.x) {
+        const int64_t ti = d / b, r = d % b;
+        const double v = W[(ti * p + ti) * b * b + r * b + r];
+        if (v == 0.0) atomicMin(&best, (int32_t)(d + 1));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *info = best == 0x7fffffff ? 0 : best;
+}
+
+}  // namespace tqr
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+using namespace tqr;
+
+namespace {
+
+thread_local std::string g_err;
+
+tqr_status set_err(tqr_status code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return set_err(TQR_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+bool tiles_ok(int b, int ib) {
+    const bool bok = b == 16 || b == 32 || b == 64 || b == 128 || b == 256;
+    const bool iok = ib == 16 || ib == 32 || ib == 64;
+    return bok && iok && ib <= b && b % ib == 0 && ib * (b + ib) <= 9216;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+int64_t wb_of(int64_t nrhs) { return cdiv(std::max<int64_t>(nrhs, 1), 16) * 16; }
+
+// Workspace: [tiles p*q*b*b][dense diagonal V q*b*b][B tiles p*b*wb][scheduler]
+struct Sizes {
+    int64_t p, q, tiles_bytes, vd_bytes, btiles_bytes, sched_bytes, total;
+};
+
+Sizes sizes_of(int64_t m, int64_t n, int64_t nrhs, int b) {
+    Sizes z;
+    z.p = cdiv(std::max<int64_t>(m, 1), b);
+    z.q = cdiv(std::max<int64_t>(n, 1), b);
+    z.tiles_bytes = align256(z.p * z.q * b * b * 8);
+    z.vd_bytes = align256(z.q * b * b * 8);
+    z.btiles_bytes = nrhs > 0 ? align256(z.p * b * wb_of(nrhs) * 8) : 0;
+    int64_t nt = FactorGraph(z.p, z.q, b).num_tasks();
+    if (nrhs > 0) {
+        nt = std::max(nt, ApplyGraph(z.p, z.q, cdiv(wb_of(nrhs), kStripCols), true).num_tasks());
+        nt = std::max(nt, TrsmGraph(z.q).num_tasks());
+    }
+    z.sched_bytes = align256(sched_bytes(nt));
+    z.total = z.tiles_bytes + z.vd_bytes + z.btiles_bytes + z.sched_bytes;
+    return z;
+}
+
+// Two seconds of the device's constant-rate clock: a worker that finds no
+// ready task for that long while the graph is unfinished gives up.
+int64_t default_timeout_ticks() {
+    static int64_t ticks = [] {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            khz = 100000;
+        return (int64_t)khz * 1000 * 2;
+    }();
+    return ticks;
+}
+
+int cu_count() {
+    static int cus = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 256;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+        return v;
+    }();
+    return cus;
+}
+
+std::vector<int64_t> serial_order(const FactorGraph &g);
+std::vector<int64_t> serial_order(const ApplyGraph &g);
+std::vector<int64_t> serial_order(const TrsmGraph &g);
+
+template <class G, class Body>
+tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, const tqr_options *opt,
+                     hipStream_t stream, int32_t *status_out) {
+    const int64_t nt = g.num_tasks();
+    if (nt == 0) return TQR_OK;
+    Sched s = sched_at(sched_mem, nt);
+    const int mode = opt ? opt->mode : TQR_MODE_PERSISTENT;
+    const int policy = opt ? opt->policy : TQR_POLICY_PAPER;
+    auto kp = k_persistent<G, Body>;
+    auto k1 = k_one_task<G, Body>;
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [&] {
+        attr_err = hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (attr_err == hipSuccess)
+            attr_err = hipFuncSetAttribute((const void *)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    });
+    HIPCHK(attr_err);
+    if (mode == TQR_MODE_SERIAL) {
+        // reference order: task ids of the factorisation graph follow
+        // Algorithm 1 step by step; within a step GEQRT, then the LARFB
+        // strips, then per row TSQRT and its SSRFB strips.
+        for (int64_t t : serial_order(g)) {
+            hipLaunchKernelGGL(k1, dim3(1), dim3(NT), lds, stream, g, body, t);
+        }
+        HIPCHK(hipGetLastError());
+        if (status_out) HIPCHK(hipMemsetAsync(status_out, 0, sizeof(int32_t), stream));
+        return TQR_OK;
+    }
+    const int blocks_init = (int)cdiv(nt, 256);
+    hipLaunchKernelGGL(k_sched_init<G>, dim3(blocks_init), dim3(256), 0, stream, g, s, policy, (int64_t)0, (int64_t)0);
+    hipLaunchKernelGGL(k_sched_seed<G>, dim3(blocks_init), dim3(256), 0, stream, g, s, policy);
+    int per_cu = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kp, NT, lds));
+    int64_t workers = (int64_t)std::max(per_cu, 1) * cu_count();
+    if (opt && opt->workgroups > 0) workers = std::min<int64_t>(workers, opt->workgroups);
+    workers = std::min<int64_t>(workers, nt);
+    RunOpts ro;
+    ro.trace = opt ? opt->trace : nullptr;
+    ro.abort_flag = opt ? opt->abort_flag : nullptr;
+    ro.timeout = (opt && opt->timeout_ticks > 0) ? opt->timeout_ticks : default_timeout_ticks();
+    ro.policy = policy;
+    hipLaunchKernelGGL(kp, dim3((unsigned)workers), dim3(NT), lds, stream, g, body, s, ro);
+    HIPCHK(hipGetLastError());
+    if (status_out) hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, stream, s.st, status_out);
+    HIPCHK(hipGetLastError());
+    return TQR_OK;
+}
+
+// Algorithm 1 order for the reference (serial) mode.
+std::vector<int64_t> serial_order(const FactorGraph &g) {
+    std::vector<int64_t> out;
+    out.reserve((size_t)g.num_tasks());
+    for (int64_t k = 0; k < g.K; ++k) {
+        out.push_back(g.encode(GEQRT, k, k, k, 0));
+        for (int64_t j = k + 1; j < g.q; ++j)
+            for (int64_t c = 0; c < g.S; ++c) out.push_back(g.encode(LARFB, k, j, k, c));
+        for (int64_t i = k + 1; i < g.p; ++i) {
+            out.push_back(g.encode(TSQRT, i, k, k, 0));
+            for (int64_t j = k + 1; j < g.q; ++j)
+                for (int64_t c = 0; c < g.S; ++c) out.push_back(g.encode(SSRFB, i, j, k, c));
+        }
+    }
+    return out;
+}
+std::vector<int64_t> serial_order(const ApplyGraph &g) {
+    std::vector<int64_t> out;
+    if (g.forward) {
+        for (int64_t k = 0; k < g.K; ++k)
+            for (int64_t i = k; i < g.p; ++i)
+                for (int64_t c = 0; c < g.S; ++c) out.push_back(g.encode(i, k, c));
+    } else {
+        for (int64_t k = g.K - 1; k >= 0; --k) {
+            for (int64_t i = g.p - 1; i > k; --i)
+                for (int64_t c = 0; c < g.S; ++c) out.push_back(g.encode(i, k, c));
+            for (int64_t c = 0; c < g.S; ++c) out.push_back(g.encode(k, k, c));
+        }
+    }
+    return out;
+}
+std::vector<int64_t> serial_order(const TrsmGraph &g) {
+    std::vector<int64_t> out;
+    for (int64_t i = g.q - 1; i >= 0; --i) {
+        for (int64_t j = g.q - 1; j > i; --j) out.push_back(g.encode_g(i, j));
+        out.push_back(g.encode_d(i));
+    }
+    // G(i,j) needs D(j): rows are solved bottom-up, so D(j) precedes every G(i,j)
+    return out;
+}
+
+// ---- dispatch over the supported (b, ib) pairs ----------------------------
+template <int B, int IB>
+tqr_status factor_impl(int64_t m, int64_t n, double *A, int64_t lda, double *T, void *work, hipStream_t stream,
+                       const tqr_options *opt, bool back_to_cm) {
+    const Sizes z = sizes_of(m, n, 0, B);
+    double *W = reinterpret_cast<double *>(work);
+    double *Vd = reinterpret_cast<double *>(reinterpret_cast<char *>(work) + z.tiles_bytes);
+    void *sched = reinterpret_cast<char *>(work) + z.tiles_bytes + z.vd_bytes;
+    hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, A, lda, m, n, W,
+                       (int)z.p, B, B);
+    FactorGraph g(z.p, z.q, B);
+    FactorBody<B, IB> body{W, T, Vd, (int)z.p};
+    tqr_status st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
+    if (st != TQR_OK) return st;
+    if (back_to_cm)
+        hipLaunchKernelGGL(k_tiles_to_cm, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, W, (int)z.p, B, B,
+                           A, lda, m, n);
+    HIPCHK(hipGetLastError());
+    return TQR_OK;
+}
+
+template <int B, int IB>
+tqr_status apply_impl(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *T, double *W, const double *Vd,
+                      double *Bm, int64_t ldb, double *Bt, void *sched, hipStream_t stream) {
+    const int64_t p = cdiv(m, B), q = cdiv(n, B), wb = wb_of(nrhs);
+    hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)p, 1), dim3(256), 0, stream, Bm, ldb, m, nrhs, Bt, (int)p, B,
+                       (int)wb);
+    ApplyGraph g(p, q, cdiv(wb, kStripCols), trans);
+    tqr_status st;
+    if (trans)
+        st = run_graph(g, ApplyBody<B, IB, true>{W, T, Vd, Bt, (int)p, (int)wb}, sched, 0, nullptr, stream, nullptr);
+    else
+        st = run_graph(g, ApplyBody<B, IB, false>{W, T, Vd, Bt, (int)p, (int)wb}, sched, 0, nullptr, stream, nullptr);
+    return st;
+}
+
+template <int B>
+tqr_status trsm_impl(int64_t m, int64_t n, int64_t nrhs, const double *W, double *Bt, void *sched, hipStream_t stream) {
+    const int64_t p = cdiv(m, B), q = cdiv(n, B), wb = wb_of(nrhs);
+    TrsmGraph g(q);
+    return run_graph(g, TrsmBody<B>{W, Bt, (int)p, (int)wb, n}, sched, (size_t)B * 16 * 8, nullptr, stream, nullptr);
+}
+
+template <class F>
+tqr_status dispatch(int b, int ib, F &&f) {
+#define TQR_CASE(BB, II) \
+    if (b == BB && ib == II) return f(std::integral_constant<int, BB>{}, std::integral_constant<int, II>{});
+    TQR_CASE(16, 16)
+    TQR_CASE(32, 16)
+    TQR_CASE(32, 32)
+    TQR_CASE(64, 16)
+    TQR_CASE(64, 32)
+    TQR_CASE(64, 64)
+    TQR_CASE(128, 16)
+    TQR_CASE(128, 32)
+    TQR_CASE(256, 16)
+    TQR_CASE(256, 32)
+#undef TQR_CASE
+    return set_err(-5, "unsupported tile_b / inner_ib pair");
+}
+
+tqr_status check_opts(const tqr_options *o) {
+    if (!o) return TQR_OK;
+    if (o->struct_size != (int32_t)sizeof(tqr_options)) return -11;
+    if (o->mode != TQR_MODE_PERSISTENT && o->mode != TQR_MODE_SERIAL) return -11;
+    if (o->policy != TQR_POLICY_PAPER && o->policy != TQR_POLICY_LOOKAHEAD) return -11;
+    if (o->workgroups < 0) return -11;
+    return TQR_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C entry points
+// ===========================================================================
+extern "C" {
+
+int64_t tqr_t_elems(int64_t m, int64_t n, int tile_b, int inner_ib) {
+    if (m < 0 || n < 0 || m < n || !tiles_ok(tile_b, inner_ib)) return -1;
+    return cdiv(std::max<int64_t>(m, 1), tile_b) * cdiv(std::max<int64_t>(n, 1), tile_b) * inner_ib * tile_b;
+}
+
+int64_t tqr_workspace_bytes(int64_t m, int64_t n, int64_t nrhs, int tile_b, int inner_ib) {
+    if (m < 0 || n < 0 || m < n || nrhs < 0 || !tiles_ok(tile_b, inner_ib)) return -1;
+    return sizes_of(m, n, nrhs, tile_b).total;
+}
+
+const char *tqr_last_error_string(void) { return g_err.c_str(); }
+
+tqr_status tqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, int tile_b, int inner_ib, double *T, void *work,
+                         int64_t work_bytes, hipStream_t stream, const tqr_options *options) {
+    if (m < 0 || m < n) return set_err(-1, "m must be >= max(n, 0)");
+    if (n < 0) return set_err(-2, "n must be >= 0");
+    if (m == 0 || n == 0) return TQR_OK;
+    if (!A) return set_err(-3, "A is null");
+    if (lda < std::max<int64_t>(1, m)) return set_err(-4, "lda < max(1, m)");
+    if (!(tile_b == 16 || tile_b == 32 || tile_b == 64 || tile_b == 128 || tile_b == 256))
+        return set_err(-5, "tile_b must be one of 16, 32, 64, 128, 256");
+    if (!tiles_ok(tile_b, inner_ib)) return set_err(-6, "inner_ib must be 16, 32 or 64, divide tile_b, and ib*(b+ib) <= 9216");
+    if (!T) return set_err(-7, "T is null");
+    if (!work) return set_err(-8, "work is null");
+    if (work_bytes < tqr_workspace_bytes(m, n, 0, tile_b, inner_ib)) return set_err(-9, "work_bytes too small");
+    if (check_opts(options) != TQR_OK) return set_err(-11, "bad tqr_options");
+    return dispatch(tile_b, inner_ib, [&](auto BB, auto II) {
+        return factor_impl<decltype(BB)::value, decltype(II)::value>(m, n, A, lda, T, work, stream, options, true);
+    });
+}
+
+tqr_status tqr_factor(int64_t m, int64_t n, double *A, int64_t lda, int tile_b, int inner_ib, double *T, void *work,
+                      int64_t work_bytes, hipStream_t stream) {
+    return tqr_factor_ex(m, n, A, lda, tile_b, inner_ib, T, work, work_bytes, stream, nullptr);
+}
+
+static tqr_status apply_common(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                               const double *T, int tile_b, int inner_ib, double *B, int64_t ldb, void *work,
+                               int64_t work_bytes, hipStream_t stream) {
+    if (m < 0 || m < n) return set_err(-1, "m must be >= max(n, 0)");
+    if (n < 0) return set_err(-2, "n must be >= 0");
+    if (nrhs < 0) return set_err(-3, "nrhs must be >= 0");
+    if (m == 0 || n == 0 || nrhs == 0) return TQR_OK;
+    if (!A) return set_err(-4, "A is null");
+    if (lda < std::max<int64_t>(1, m)) return set_err(-5, "lda < max(1, m)");
+    if (!T) return set_err(-6, "T is null");
+    if (!(tile_b == 16 || tile_b == 32 || tile_b == 64 || tile_b == 128 || tile_b == 256))
+        return set_err(-7, "tile_b must be one of 16, 32, 64, 128, 256");
+    if (!tiles_ok(tile_b, inner_ib)) return set_err(-8, "unsupported inner_ib");
+    if (!B) return set_err(-9, "B is null");
+    if (ldb < std::max<int64_t>(1, m)) return set_err(-10, "ldb < max(1, m)");
+    if (!work) return set_err(-11, "work is null");
+    if (work_bytes < tqr_workspace_bytes(m, n, nrhs, tile_b, inner_ib)) return set_err(-12, "work_bytes too small");
+    const Sizes z = sizes_of(m, n, nrhs, tile_b);
+    double *W = reinterpret_cast<double *>(work);
+    double *Vd = reinterpret_cast<double *>(reinterpret_cast<char *>(work) + z.tiles_bytes);
+    double *Bt = reinterpret_cast<double *>(reinterpret_cast<char *>(work) + z.tiles_bytes + z.vd_bytes);
+    void *sched = reinterpret_cast<char *>(work) + z.tiles_bytes + z.vd_bytes + z.btiles_bytes;
+    hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, A, lda, m, n, W,
+                       (int)z.p, tile_b, tile_b);
+    hipLaunchKernelGGL(k_unit_lower, dim3((unsigned)std::min(z.p, z.q)), dim3(256), 0, stream, W, (int)z.p, tile_b, Vd);
+    tqr_status st = dispatch(tile_b, inner_ib, [&](auto BB, auto II) {
+        return apply_impl<decltype(BB)::value, decltype(II)::value>(trans, m, n, nrhs, T, W, Vd, B, ldb, Bt, sched,
+                                                                    stream);
+    });
+    if (st != TQR_OK) return st;
+    hipLaunchKernelGGL(k_tiles_to_cm, dim3((unsigned)z.p, 1), dim3(256), 0, stream, Bt, (int)z.p, tile_b,
+                       (int)wb_of(nrhs), B, ldb, m, nrhs);
+    HIPCHK(hipGetLastError());
+    return TQR_OK;
+}
+
+tqr_status tqr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *T, int tile_b,
+                        int inner_ib, double *B, int64_t ldb, void *work, int64_t work_bytes, hipStream_t stream) {
+    return apply_common(true, m, n, nrhs, A, lda, T, tile_b, inner_ib, B, ldb, work, work_bytes, stream);
+}
+
+tqr_status tqr_apply_q(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *T, int tile_b,
+                       int inner_ib, double *B, int64_t ldb, void *work, int64_t work_bytes, hipStream_t stream) {
+    return apply_common(false, m, n, nrhs, A, lda, T, tile_b, inner_ib, B, ldb, work, work_bytes, stream);
+}
+
+tqr_status tqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb, int tile_b,
+                        int inner_ib, double *T, void *work, int64_t work_bytes, int32_t *d_info, hipStream_t stream) {
+    if (m < 0 || m < n) return set_err(-1, "m must be >= max(n, 0)");
+    if (n < 0) return set_err(-2, "n must be >= 0");
+    if (nrhs < 0) return set_err(-3, "nrhs must be >= 0");
+    if (!A && m > 0 && n > 0) return set_err(-4, "A is null");
+    if (lda < std::max<int64_t>(1, m)) return set_err(-5, "lda < max(1, m)");
+    if (!B && m > 0 && nrhs > 0) return set_err(-6, "B is null");
+    if (ldb < std::max<int64_t>(1, m)) return set_err(-7, "ldb < max(1, m)");
+    if (!(tile_b == 16 || tile_b == 32 || tile_b == 64 || tile_b == 128 || tile_b == 256))
+        return set_err(-8, "tile_b must be one of 16, 32, 64, 128, 256");
+    if (!tiles_ok(tile_b, inner_ib)) return set_err(-9, "unsupported inner_ib");
+    if (!T && m > 0 && n > 0) return set_err(-10, "T is null");
+    if (!work && m > 0 && n > 0) return set_err(-11, "work is null");
+    if (m > 0 && n > 0 && work_bytes < tqr_workspace_bytes(m, n, nrhs, tile_b, inner_ib))
+        return set_err(-12, "work_bytes too small");
+    if (!d_info) return set_err(-13, "d_info is null");
+    if (m == 0 || n == 0) {
+        HIPCHK(hipMemsetAsync(d_info, 0, sizeof(int32_t), stream));
+        return TQR_OK;
+    }
+    const Sizes z = sizes_of(m, n, nrhs, tile_b);
+    double *W = reinterpret_cast<double *>(work);
+    double *Vd = reinterpret_cast<double *>(reinterpret_cast<char *>(work) + z.tiles_bytes);
+    double *Bt = reinterpret_cast<double *>(reinterpret_cast<char *>(work) + z.tiles_bytes + z.vd_bytes);
+    void *sched = reinterpret_cast<char *>(work) + z.tiles_bytes + z.vd_bytes + z.btiles_bytes;
+    tqr_status st = dispatch(tile_b, inner_ib, [&](auto BB, auto II) -> tqr_status {
+        constexpr int Bv = decltype(BB)::value, Iv = decltype(II)::value;
+        // the factorisation's tiles stay in the workspace for the solve
+        hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, A, lda, m, n, W,
+                           (int)z.p, Bv, Bv);
+        FactorGraph g(z.p, z.q, Bv);
+        tqr_status s1 = run_graph(g, FactorBody<Bv, Iv>{W, T, Vd, (int)z.p}, sched, TileKernels<Bv, Iv>::LDS_BYTES,
+                                  nullptr, stream, nullptr);
+        if (s1 != TQR_OK) return s1;
+        hipLaunchKernelGGL(k_tiles_to_cm, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, W, (int)z.p, Bv,
+                           Bv, A, lda, m, n);
+        if (nrhs == 0) return TQR_OK;
+        s1 = apply_impl<Bv, Iv>(true, m, n, nrhs, T, W, Vd, B, ldb, Bt, sched, stream);
+        if (s1 != TQR_OK) return s1;
+        hipLaunchKernelGGL(k_diag_info, dim3(1), dim3(256), 0, stream, W, (int)z.p, Bv, n, d_info);
+        s1 = trsm_impl<Bv>(m, n, nrhs, W, Bt, sched, stream);
+        if (s1 != TQR_OK) return s1;
+        hipLaunchKernelGGL(k_tiles_to_cm, dim3((unsigned)z.p, 1), dim3(256), 0, stream, Bt, (int)z.p, Bv,
+                           (int)wb_of(nrhs), B, ldb, m, nrhs);
+        return TQR_OK;
+    });
+    if (st != TQR_OK) return st;
+    if (nrhs == 0) HIPCHK(hipMemsetAsync(d_info, 0, sizeof(int32_t), stream));
+    HIPCHK(hipGetLastError());
+    return TQR_OK;
+}
+
+// ---- graph introspection ----------------------------------------------------
+int64_t tqr_graph_tasks(int64_t p, int64_t q, int tile_b) {
+    if (p < 1 || q < 1 || q > p || tile_b < 1) return -1;
+    return FactorGraph(p, q, tile_b).num_tasks();
+}
+
+int tqr_graph_task(int64_t p, int64_t q, int tile_b, int64_t task, int32_t out[5]) {
+    const int64_t nt = tqr_graph_tasks(p, q, tile_b);
+    if (nt < 0 || task < 0 || task >= nt || !out) return -1;
+    const Task t = FactorGraph(p, q, tile_b).decode(task);
+    out[0] = t.kind; out[1] = t.i; out[2] = t.j; out[3] = t.k; out[4] = t.c;
+    return 0;
+}
+
+int tqr_graph_indegree(int64_t p, int64_t q, int tile_b, int64_t task) {
+    const int64_t nt = tqr_graph_tasks(p, q, tile_b);
+    if (nt < 0 || task < 0 || task >= nt) return -1;
+    FactorGraph g(p, q, tile_b);
+    return g.indegree(g.decode(task));
+}
+
+int tqr_graph_successors(int64_t p, int64_t q, int tile_b, int64_t task, int64_t *out, int max_out) {
+    const int64_t nt = tqr_graph_tasks(p, q, tile_b);
+    if (nt < 0 || task < 0 || task >= nt) return -1;
+    FactorGraph g(p, q, tile_b);
+    const Task t = g.decode(task);
+    const int ns = g.num_successors(t);
+    for (int n = 0; n < ns && n < max_out; ++n) out[n] = g.successor(t, n);
+    return ns;
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+"""ctypes binding of ``libtqr.so`` (include/tqr.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of the computation runs in the library's kernels.  The
+library must be built (``python -m paper_0707_3548_amd.build``); importing
+this module on a machine without it raises at the first call, never falls
+back to anything else.
+
+Matrices are column-major: a torch tensor ``X`` of shape (m, n) whose
+``X.stride() == (1, ld)`` with ``ld >= m`` (``fortran(x)`` makes one).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtqr.so")
+
+MODE_PERSISTENT, MODE_SERIAL = 0, 1
+POLICY_PAPER, POLICY_LOOKAHEAD = 0, 1
+TQR_EDEVICE, TQR_EABORTED = -1000, -1001
+
+
+class TqrError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} returned {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_int32),
+        ("workgroups", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("policy", ctypes.c_int32),
+        ("trace", ctypes.c_void_p),
+        ("abort_flag", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+        ("timeout_ticks", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_0707_3548_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, i32, vp, dp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p
+        L.tqr_t_elems.argtypes = [i64, i64, i32, i32]
+        L.tqr_t_elems.restype = i64
+        L.tqr_workspace_bytes.argtypes = [i64, i64, i64, i32, i32]
+        L.tqr_workspace_bytes.restype = i64
+        L.tqr_factor.argtypes = [i64, i64, dp, i64, i32, i32, dp, vp, i64, vp]
+        L.tqr_factor.restype = i32
+        L.tqr_factor_ex.argtypes = [i64, i64, dp, i64, i32, i32, dp, vp, i64, vp, ctypes.POINTER(Options)]
+        L.tqr_factor_ex.restype = i32
+        for f in ("tqr_apply_qt", "tqr_apply_q"):
+            getattr(L, f).argtypes = [i64, i64, i64, dp, i64, dp, i32, i32, dp, i64, vp, i64, vp]
+            getattr(L, f).restype = i32
+        L.tqr_solve_ls.argtypes = [i64, i64, i64, dp, i64, dp, i64, i32, i32, dp, vp, i64, vp, vp]
+        L.tqr_solve_ls.restype = i32
+        L.tqr_last_error_string.argtypes = []
+        L.tqr_last_error_string.restype = ctypes.c_char_p
+        L.tqr_graph_tasks.argtypes = [i64, i64, i32]
+        L.tqr_graph_tasks.restype = i64
+        L.tqr_graph_task.argtypes = [i64, i64, i32, i64, ctypes.POINTER(ctypes.c_int32)]
+        L.tqr_graph_task.restype = i32
+        L.tqr_graph_indegree.argtypes = [i64, i64, i32, i64]
+        L.tqr_graph_indegree.restype = i32
+        L.tqr_graph_successors.argtypes = [i64, i64, i32, i64, ctypes.POINTER(ctypes.c_int64), i32]
+        L.tqr_graph_successors.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, rc: int) -> None:
+    if rc != 0:
+        msg = lib().tqr_last_error_string()
+        raise TqrError(fn, rc, msg.decode() if msg else "")
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def fortran(x: torch.Tensor) -> torch.Tensor:
+    """A column-major copy of a 2-D tensor (shape kept)."""
+    return x.t().contiguous().t()
+
+
+def _ld(X: torch.Tensor) -> int:
+    if X.dim() != 2 or X.dtype != torch.float64 or not X.is_cuda:
+        raise ValueError("expected a 2-D float64 CUDA tensor")
+    if X.shape[0] > 1 and X.stride(0) != 1:
+        raise ValueError("expected a column-major tensor (use tqr.fortran)")
+    return max(1, X.stride(1) if X.shape[1] > 1 else X.shape[0])
+
+
+def t_elems(m: int, n: int, tile_b: int, inner_ib: int) -> int:
+    return int(lib().tqr_t_elems(m, n, tile_b, inner_ib))
+
+
+def workspace_bytes(m: int, n: int, nrhs: int, tile_b: int, inner_ib: int) -> int:
+    return int(lib().tqr_workspace_bytes(m, n, nrhs, tile_b, inner_ib))
+
+
+class Workspace:
+    """Device buffers sized for a problem shape, reusable across calls."""
+
+    def __init__(self, m: int, n: int, nrhs: int, tile_b: int, inner_ib: int, device="cuda"):
+        self.m, self.n, self.nrhs, self.tile_b, self.inner_ib = m, n, nrhs, tile_b, inner_ib
+        nb = workspace_bytes(m, n, nrhs, tile_b, inner_ib)
+        te = t_elems(m, n, tile_b, inner_ib)
+        if nb < 0 or te < 0:
+            raise ValueError("unsupported sizes or tiling")
+        self.work = torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+        self.T = torch.zeros(max(te, 1), dtype=torch.float64, device=device)
+
+
+def factor(A: torch.Tensor, tile_b: int, inner_ib: int, ws: Workspace | None = None, *, workgroups: int = 0,
+           mode: int = MODE_PERSISTENT, policy: int = POLICY_PAPER, trace: torch.Tensor | None = None,
+           status: torch.Tensor | None = None, abort_flag=None, timeout_ticks: int = 0):
+    """In-place tiled QR of the column-major A; returns (A, T)."""
+    m, n = A.shape
+    lda = _ld(A)
+    if ws is None:
+        ws = Workspace(m, n, 0, tile_b, inner_ib, A.device)
+    opt = Options(ctypes.sizeof(Options), workgroups, mode, policy,
+                  trace.data_ptr() if trace is not None else None,
+                  abort_flag, status.data_ptr() if status is not None else None, timeout_ticks)
+    rc = lib().tqr_factor_ex(m, n, A.data_ptr(), lda, tile_b, inner_ib, ws.T.data_ptr(), ws.work.data_ptr(),
+                             ws.work.numel(), _stream(), ctypes.byref(opt))
+    _check("tqr_factor", rc)
+    return A, ws.T
+
+
+def _apply(fn: str, A, T, B, tile_b, inner_ib, ws: Workspace | None):
+    m, n = A.shape
+    nrhs = B.shape[1]
+    if ws is None:
+        ws = Workspace(m, n, nrhs, tile_b, inner_ib, A.device)
+    rc = getattr(lib(), fn)(m, n, nrhs, A.data_ptr(), _ld(A), T.data_ptr(), tile_b, inner_ib, B.data_ptr(), _ld(B),
+                            ws.work.data_ptr(), ws.work.numel(), _stream())
+    _check(fn, rc)
+    return B
+
+
+def apply_qt(A, T, B, tile_b, inner_ib, ws=None):
+    """B <- Q^T B in place (B column-major m x nrhs)."""
+    return _apply("tqr_apply_qt", A, T, B, tile_b, inner_ib, ws)
+
+
+def apply_q(A, T, B, tile_b, inner_ib, ws=None):
+    """B <- Q B in place."""
+    return _apply("tqr_apply_q", A, T, B, tile_b, inner_ib, ws)
+
+
+def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None):
+    """min ||A X - B||: A overwritten by its factors, X in B[0:n].  Returns
+    (B, info tensor on the device)."""
+    m, n = A.shape
+    nrhs = B.shape[1]
+    if ws is None:
+        ws = Workspace(m, n, nrhs, tile_b, inner_ib, A.device)
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rc = lib().tqr_solve_ls(m, n, nrhs, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), tile_b, inner_ib,
+                            ws.T.data_ptr(), ws.work.data_ptr(), ws.work.numel(), info.data_ptr(), _stream())
+    _check("tqr_solve_ls", rc)
+    return B, info
+
+
+# ---- task-graph introspection (host only) ------------------------------------
+
+def graph_tasks(p: int, q: int, tile_b: int) -> int:
+    return int(lib().tqr_graph_tasks(p, q, tile_b))
+
+
+def graph_task(p: int, q: int, tile_b: int, t: int):
+    out = (ctypes.c_int32 * 5)()
+    if lib().tqr_graph_task(p, q, tile_b, t, out) != 0:
+        raise IndexError(t)
+    return tuple(out)
+
+
+def graph_indegree(p: int, q: int, tile_b: int, t: int) -> int:
+    return int(lib().tqr_graph_indegree(p, q, tile_b, t))
+
+
+def graph_successors(p: int, q: int, tile_b: int, t: int):
+    buf = (ctypes.c_int64 * 4096)()
+    ns = lib().tqr_graph_successors(p, q, tile_b, t, buf, 4096)
+    if ns < 0:
+        raise IndexError(t)
+    return [buf[i] for i in range(ns)]

@@ -1,0 +1,228 @@
+"""Parity of the HIP tiled QR with the oracle (GPU).
+
+R is compared after sign normalisation with the unblocked FP64 oracle; the V
+and T tiles element by element with the tiled model of Algorithm 1
+(oracle/tiled.py); Q through the library's own apply_q.  Tolerances: the
+sign-normalised R to 1e-10 relative (Frobenius); ||A - QR||_F/||A||_F and
+||Q^T Q - I||_F to 10 n eps; V/T tiles to 1e-11 relative to the tile scale
+(both sides apply the same reflectors in the same order, only the summation
+order inside the products differs)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import tiled
+
+pytestmark = pytest.mark.gpu
+
+EPS = oracle.EPS
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def run_factor(A, b, ib, **kw):
+    torch = _torch()
+    from paper_0707_3548_amd import tqr
+    dA = tqr.fortran(torch.from_numpy(np.asarray(A, dtype=np.float64)).cuda())
+    ws = tqr.Workspace(A.shape[0], A.shape[1], 0, b, ib)
+    tqr.factor(dA, b, ib, ws, **kw)
+    torch.cuda.synchronize()
+    return dA, ws
+
+
+def gpu_thin_q(dA, T, b, ib):
+    torch = _torch()
+    from paper_0707_3548_amd import tqr
+    m, n = dA.shape
+    E = torch.zeros((n, m), dtype=torch.float64, device="cuda").t()
+    E[torch.arange(n), torch.arange(n)] = 1.0
+    tqr.apply_q(dA, T, E, b, ib)
+    torch.cuda.synchronize()
+    return E.cpu().numpy()
+
+
+def t_slots(T, m, n, b, ib):
+    p, q = -(-m // b), -(-n // b)
+    return T.reshape(q, p, b, ib).permute(1, 0, 3, 2).cpu().numpy()  # [i, k] -> ib x b
+
+
+SHAPES = [
+    (512, 512, 64, 16),     # the 8 x 8 tile workload
+    (100, 70, 32, 16),
+    (300, 300, 64, 32),
+    (1000, 200, 128, 32),
+    (257, 129, 256, 32),
+    (64, 64, 64, 64),
+    (16, 16, 16, 16),
+    (1, 1, 16, 16),
+    (37, 1, 16, 16),
+    (520, 300, 256, 16),
+    (96, 96, 32, 32),
+]
+
+
+@pytest.mark.parametrize("m,n,b,ib", SHAPES)
+def test_factor_matches_oracle(m, n, b, ib):
+    from paper_0707_3548_amd import workloads
+    _say(f"case factor m={m} n={n} b={b} ib={ib}")
+    A = workloads.gaussian(m, n, seed=m * 13 + n)
+    dA, ws = run_factor(A, b, ib)
+    F = dA.cpu().numpy()
+    R = np.triu(F[:n, :])
+    _, R_or = oracle.qr(A)
+    assert oracle.rel_fro(oracle.sign_normalize(R), R_or) < 1e-10
+    # V and T tiles: the tiled model of Algorithm 1 with the same tiling
+    tiles, Tm = tiled.factor(A, b, ib)
+    F_model = tiled.from_tiles(tiles, m, n)
+    scale = max(1.0, np.abs(F_model).max())
+    assert np.abs(F - F_model).max() < 1e-11 * scale * max(1, n // 64)
+    Tg = t_slots(ws.T, m, n, b, ib)
+    p, q = Tg.shape[:2]
+    for k in range(min(p, q)):
+        for i in range(k, p):
+            assert np.abs(Tg[i, k] - Tm[i, k]).max() < 1e-11 * max(1, n // 64) * max(1.0, np.abs(Tm[i, k]).max())
+    # Q from the library: backward error and orthogonality
+    Q = gpu_thin_q(dA, ws.T, b, ib)
+    assert oracle.fact_error(A, Q, R) <= 10 * n * EPS
+    assert oracle.orth_error(Q) <= 10 * n * EPS
+
+
+def test_upper_triangular_input_is_exact():
+    from paper_0707_3548_amd import workloads
+    _say("case upper-triangular 192x128 b=64 ib=16")
+    U = np.triu(workloads.gaussian(192, 128, seed=3))
+    dA, ws = run_factor(U, 64, 16)
+    assert np.array_equal(dA.cpu().numpy(), U)
+    assert float(ws.T.abs().max()) == 0.0
+
+
+def test_zero_matrix_does_not_nan():
+    _say("case zero 100x60")
+    dA, ws = run_factor(np.zeros((100, 60)), 32, 16)
+    assert np.all(dA.cpu().numpy() == 0)
+
+
+def test_schedules_are_bitwise_identical():
+    """Every legal order applies the same operations to each tile, so the
+    result is independent of the schedule: one launch per task in Algorithm 1
+    order, the persistent scheduler with 1, 7 and all workgroups, and the
+    lookahead priority policy all give the same bits."""
+    from paper_0707_3548_amd import tqr, workloads
+    A = workloads.gaussian(640, 448, seed=5)
+    outs = []
+    for kw in [dict(mode=tqr.MODE_SERIAL), dict(workgroups=1), dict(workgroups=7), dict(),
+               dict(policy=tqr.POLICY_LOOKAHEAD)]:
+        _say(f"case schedule {kw}")
+        dA, ws = run_factor(A, 64, 16, **kw)
+        outs.append((dA.cpu().numpy(), ws.T.cpu().numpy()))
+    for F, T in outs[1:]:
+        assert np.array_equal(F, outs[0][0])
+        assert np.array_equal(T, outs[0][1])
+
+
+def test_trace_respects_the_task_graph():
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    m = n = 384
+    b = 64
+    _say("case trace 384x384 b=64")
+    p = q = m // b
+    nt = tqr.graph_tasks(p, q, b)
+    trace = torch.zeros(4 * nt, dtype=torch.int64, device="cuda")
+    run_factor(workloads.gaussian(m, n, seed=6), b, 16, trace=trace)
+    tr = trace.cpu().numpy().reshape(nt, 4)
+    start, end = tr[:, 0], tr[:, 1]
+    assert np.all(end >= start) and np.all(start > 0)
+    for u in range(nt):
+        for v in tqr.graph_successors(p, q, b, u):
+            assert start[v] >= end[u], (tqr.graph_task(p, q, b, u), tqr.graph_task(p, q, b, v))
+
+
+def test_timeout_path_reports_abort():
+    """A wait bound of one clock tick makes idle workers give up at once: the
+    launch ends, status reports TQR_EABORTED, and the stream stays usable."""
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    _say("case timeout 512x512")
+    A = workloads.gaussian(512, 512, seed=7)
+    status = torch.full((1,), 12345, dtype=torch.int32, device="cuda")
+    run_factor(A, 64, 16, timeout_ticks=1, status=status)
+    assert int(status.item()) in (0, tqr.TQR_EABORTED)
+    dA, _ = run_factor(A, 64, 16, status=status)
+    assert int(status.item()) == 0
+    _, R_or = oracle.qr(A)
+    assert oracle.rel_fro(oracle.sign_normalize(np.triu(dA.cpu().numpy())), R_or) < 1e-10
+
+
+def test_host_abort_flag():
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    import ctypes
+    _say("case abort flag")
+    flag = torch.ones(1, dtype=torch.int32, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    A = workloads.gaussian(256, 256, seed=8)
+    run_factor(A, 64, 16, abort_flag=ctypes.c_void_p(flag.data_ptr()), status=status)
+    assert int(status.item()) in (0, tqr.TQR_EABORTED)
+
+
+@pytest.mark.parametrize("m,n,b,ib,nrhs", [(512, 512, 64, 16, 3), (300, 200, 64, 32, 1), (700, 300, 128, 16, 20),
+                                           (257, 129, 256, 32, 70)])
+def test_apply_qt_and_q(m, n, b, ib, nrhs):
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    _say(f"case apply m={m} n={n} b={b} ib={ib} nrhs={nrhs}")
+    A = workloads.gaussian(m, n, seed=9)
+    Bh = workloads.gaussian(m, nrhs, seed=10)
+    dA, ws = run_factor(A, b, ib)
+    dB = tqr.fortran(torch.from_numpy(Bh).cuda())
+    tqr.apply_qt(dA, ws.T, dB, b, ib)
+    torch.cuda.synchronize()
+    tiles, Tm = tiled.factor(A, b, ib)
+    C_model = tiled.apply_qt(tiles, Tm, Bh)
+    assert oracle.rel_fro(dB.cpu().numpy(), C_model) < 1e-12
+    tqr.apply_q(dA, ws.T, dB, b, ib)
+    torch.cuda.synchronize()
+    assert oracle.rel_fro(dB.cpu().numpy(), Bh) < 1e-13
+
+
+@pytest.mark.parametrize("m,n,b,ib,nrhs,cond", [(512, 256, 64, 16, 1, 1e2), (600, 400, 64, 32, 4, 1e5),
+                                                (1000, 300, 128, 32, 2, 1e3), (333, 333, 32, 16, 1, 1e2)])
+def test_solve_ls_matches_oracle(m, n, b, ib, nrhs, cond):
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    _say(f"case solve_ls m={m} n={n} b={b} ib={ib} nrhs={nrhs} cond={cond}")
+    A, Bh, _ = workloads.ls_problem(m, n, cond, seed=11, nrhs=nrhs)
+    dA = tqr.fortran(torch.from_numpy(A).cuda())
+    dB = tqr.fortran(torch.from_numpy(Bh).cuda())
+    _, info = tqr.solve_ls(dA, dB, b, ib)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    X = dB.cpu().numpy()[:n]
+    Xo, _ = oracle.lstsq(A, Bh)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) < cond * 1e-13
+    for c in range(nrhs):
+        assert oracle.ls_backward_error(A, X[:, c], Bh[:, c]) < 1e-15
+
+
+def test_solve_ls_reports_zero_diagonal():
+    torch = _torch()
+    from paper_0707_3548_amd import tqr
+    _say("case solve_ls singular")
+    A = np.zeros((128, 64))
+    A[:64, :64] = np.triu(np.random.default_rng(1).standard_normal((64, 64))) + 3 * np.eye(64)
+    A[:, 10] = 0.0
+    dA = tqr.fortran(torch.from_numpy(A).cuda())
+    dB = tqr.fortran(torch.ones((128, 1), dtype=torch.float64, device="cuda"))
+    _, info = tqr.solve_ls(dA, dB, 32, 16)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 11
