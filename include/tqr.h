@@ -95,7 +95,9 @@ typedef struct tqr_options {
     const volatile int32_t *abort_flag; /* host-mapped or device int polled while
                                            waiting for work; nonzero aborts; or NULL */
     int32_t *status;           /* device int or NULL: 0 done, TQR_EABORTED */
-    int64_t timeout_ticks;     /* per-wait bound in device clock ticks; 0 = 10 s */
+    int64_t timeout_ticks;     /* per-wait bound in device clock ticks; 0 = 2 s */
+    void *event_begin;         /* hipEvent_t recorded on `stream` right before the  */
+    void *event_end;           /* scheduler launch and right after it, or NULL     */
 } tqr_options;
 
 #define TQR_MODE_PERSISTENT 0  /* one launch; tasks run out of order as the graph allows */

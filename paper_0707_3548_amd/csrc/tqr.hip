@@ -638,6 +638,7 @@ tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, 
     });
     HIPCHK(attr_err);
     if (mode == TQR_MODE_SERIAL) {
+        if (opt && opt->event_begin) HIPCHK(hipEventRecord((hipEvent_t)opt->event_begin, stream));
         // reference order: task ids of the factorisation graph follow
         // Algorithm 1 step by step; within a step GEQRT, then the LARFB
         // strips, then per row TSQRT and its SSRFB strips.
@@ -645,6 +646,7 @@ tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, 
             hipLaunchKernelGGL(k1, dim3(1), dim3(NT), lds, stream, g, body, t);
         }
         HIPCHK(hipGetLastError());
+        if (opt && opt->event_end) HIPCHK(hipEventRecord((hipEvent_t)opt->event_end, stream));
         if (status_out) HIPCHK(hipMemsetAsync(status_out, 0, sizeof(int32_t), stream));
         return TQR_OK;
     }
@@ -661,8 +663,10 @@ tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, 
     ro.abort_flag = opt ? opt->abort_flag : nullptr;
     ro.timeout = (opt && opt->timeout_ticks > 0) ? opt->timeout_ticks : default_timeout_ticks();
     ro.policy = policy;
+    if (opt && opt->event_begin) HIPCHK(hipEventRecord((hipEvent_t)opt->event_begin, stream));
     hipLaunchKernelGGL(kp, dim3((unsigned)workers), dim3(NT), lds, stream, g, body, s, ro);
     HIPCHK(hipGetLastError());
+    if (opt && opt->event_end) HIPCHK(hipEventRecord((hipEvent_t)opt->event_end, stream));
     if (status_out) hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, stream, s.st, status_out);
     HIPCHK(hipGetLastError());
     return TQR_OK;

@@ -40,6 +40,8 @@ class Options(ctypes.Structure):
         ("abort_flag", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
         ("timeout_ticks", ctypes.c_int64),
+        ("event_begin", ctypes.c_void_p),
+        ("event_end", ctypes.c_void_p),
     ]
 
 
@@ -126,15 +128,19 @@ class Workspace:
 
 def factor(A: torch.Tensor, tile_b: int, inner_ib: int, ws: Workspace | None = None, *, workgroups: int = 0,
            mode: int = MODE_PERSISTENT, policy: int = POLICY_PAPER, trace: torch.Tensor | None = None,
-           status: torch.Tensor | None = None, abort_flag=None, timeout_ticks: int = 0):
-    """In-place tiled QR of the column-major A; returns (A, T)."""
+           status: torch.Tensor | None = None, abort_flag=None, timeout_ticks: int = 0,
+           events=None):
+    """In-place tiled QR of the column-major A; returns (A, T).  ``events`` is
+    an optional pair of raw hipEvent_t handles recorded around the scheduler
+    launch (see HipEvents)."""
     m, n = A.shape
     lda = _ld(A)
     if ws is None:
         ws = Workspace(m, n, 0, tile_b, inner_ib, A.device)
     opt = Options(ctypes.sizeof(Options), workgroups, mode, policy,
                   trace.data_ptr() if trace is not None else None,
-                  abort_flag, status.data_ptr() if status is not None else None, timeout_ticks)
+                  abort_flag, status.data_ptr() if status is not None else None, timeout_ticks,
+                  events[0] if events else None, events[1] if events else None)
     rc = lib().tqr_factor_ex(m, n, A.data_ptr(), lda, tile_b, inner_ib, ws.T.data_ptr(), ws.work.data_ptr(),
                              ws.work.numel(), _stream(), ctypes.byref(opt))
     _check("tqr_factor", rc)
@@ -199,3 +205,43 @@ def graph_successors(p: int, q: int, tile_b: int, t: int):
     if ns < 0:
         raise IndexError(t)
     return [buf[i] for i in range(ns)]
+
+
+# ---- raw HIP events on the caller's stream (timing of the scheduler launch) --
+
+class HipEvents:
+    """hipEvent_t handles from the HIP runtime already loaded by torch, so the
+    events can be recorded by the library on torch's stream."""
+
+    def __init__(self):
+        import glob
+        self.rt = None
+        for name in ("libamdhip64.so.7", "libamdhip64.so"):
+            try:
+                self.rt = ctypes.CDLL(name, mode=ctypes.RTLD_GLOBAL)
+                break
+            except OSError:
+                continue
+        if self.rt is None:
+            cands = glob.glob(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so*"))
+            self.rt = ctypes.CDLL(cands[0], mode=ctypes.RTLD_GLOBAL)
+        self.rt.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.rt.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self):
+        ev = ctypes.c_void_p()
+        if self.rt.hipEventCreate(ctypes.byref(ev)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return ev.value
+
+    def elapsed_ms(self, a, b) -> float:
+        self.rt.hipEventSynchronize(ctypes.c_void_p(b))
+        out = ctypes.c_float()
+        if self.rt.hipEventElapsedTime(ctypes.byref(out), ctypes.c_void_p(a), ctypes.c_void_p(b)) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(out.value)
+
+    def destroy(self, ev):
+        self.rt.hipEventDestroy(ctypes.c_void_p(ev))
