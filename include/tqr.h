@@ -90,8 +90,10 @@ typedef struct tqr_options {
     int32_t workgroups;        /* persistent workers; 0 = one per resident slot */
     int32_t mode;              /* TQR_MODE_PERSISTENT or TQR_MODE_SERIAL */
     int32_t policy;            /* TQR_POLICY_PAPER (default) or TQR_POLICY_LOOKAHEAD */
-    int64_t *trace;            /* device, 4 int64 per task or NULL: start, end
-                                  (device real-time clock ticks), workgroup, XCD */
+    int64_t *trace;            /* device, 8 int64 per task or NULL: taken, acquired,
+                                  body done, released (device constant-rate clock
+                                  ticks), workgroup, XCD, the wave's
+                                  HW_ID register (CU/SE ids), 0 */
     const volatile int32_t *abort_flag; /* host-mapped or device int polled while
                                            waiting for work; nonzero aborts; or NULL */
     int32_t *status;           /* device int or NULL: 0 done, TQR_EABORTED */

@@ -50,14 +50,20 @@ __global__ void k_tiles_to_cm(const double *__restrict__ W, int p, int b, int tw
 // ===========================================================================
 // Scheduler state (in the caller's workspace)
 // ===========================================================================
+// The words that idle workers poll (epoch, done, status), the queue heads and
+// the queue tails each sit in their own 256-byte block, so that polling and
+// the atomics of busy workers do not queue behind each other.
 struct SchedState {
+    uint32_t epoch;   // number of tasks published so far
+    uint32_t done;    // number of tasks finished
+    int32_t status;   // 0, or TQR_EABORTED
+    uint32_t pad0[61];
     uint32_t head[8];
+    uint32_t pad1[56];
     uint32_t tail[8];
-    uint32_t done;
-    int32_t status;
-    uint32_t pad[14];
+    uint32_t pad2[56];
 };
-static_assert(sizeof(SchedState) == 128, "state layout");
+static_assert(sizeof(SchedState) == 768, "state layout");
 
 struct Sched {
     SchedState *st;
@@ -93,6 +99,7 @@ __global__ void k_sched_init(G g, Sched s, int policy, int64_t src0, int64_t src
             s.st->head[l] = 0;
             s.st->tail[l] = 0;
         }
+        s.st->epoch = 0;
         s.st->done = 0;
         s.st->status = 0;
     }
@@ -120,55 +127,94 @@ __global__ void k_sched_seed(G g, Sched s, int policy) {
     if (g.indegree(task) != 0) return;
     const int lvl = level_of(g, task, policy);
     const uint32_t pos = __hip_atomic_fetch_add(&s.st->tail[lvl], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&s.queue[lvl * s.cap + pos], (int32_t)t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&s.queue[lvl * s.cap + pos], (int32_t)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_fetch_add(&s.st->epoch, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Scheduler flags are read and written with system-scope atomics: a
-// system-scope access is never served from a possibly stale copy in one
-// XCD's L2, so a flag written on one XCD is seen on every other.
+// Scheduler flags (queue heads and tails, slots, dependency counters, the done
+// count and the status) are accessed with relaxed system-scope atomics: a
+// system-scope access is never served from one XCD's L2, so a flag written on
+// one XCD is seen on every other.  Tile data is ordered by explicit fences: a
+// task releases its writes (agent-scope release fence) before it decrements
+// its successors' counters, and a worker acquires (agent-scope acquire fence)
+// after it takes a task.
 #define TQR_FLAG_SCOPE __HIP_MEMORY_SCOPE_SYSTEM
 
 __device__ __forceinline__ uint64_t rt_clock() { return wall_clock64(); }
 
+template <class T>
+__device__ __forceinline__ T flag_load(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+}
+
 __device__ __forceinline__ void push_task(const Sched &s, int lvl, int64_t t) {
     const uint32_t pos = __hip_atomic_fetch_add(&s.st->tail[lvl], 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
-    __hip_atomic_store(&s.queue[lvl * s.cap + pos], (int32_t)t, __ATOMIC_RELEASE, TQR_FLAG_SCOPE);
+    __hip_atomic_store(&s.queue[lvl * s.cap + pos], (int32_t)t, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+    __hip_atomic_fetch_add(&s.st->epoch, 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
 }
 
 __device__ __forceinline__ void set_status(const Sched &s, int32_t v) {
     __hip_atomic_store(&s.st->status, v, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
 }
 
-constexpr uint32_t kMaxSpins = 1u << 26;  // ~ seconds of s_sleep-paced polling
+constexpr uint32_t kMaxSpins = 1u << 26;  // a second bound on every wait, independent of the clock
 
-// Highest-priority ready task; -1 if none is ready; -2 if a reserved slot was
-// not published before the deadline (then the status is set to aborted).
-__device__ int32_t try_pop(const Sched &s, uint64_t deadline) {
-    for (int lvl = 0; lvl < kLevels; ++lvl) {
-        uint32_t *hp = &s.st->head[lvl];
-        uint32_t h = __hip_atomic_load(hp, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
-        while (h < __hip_atomic_load(&s.st->tail[lvl], __ATOMIC_RELAXED, TQR_FLAG_SCOPE)) {
-            if (__hip_atomic_compare_exchange_strong(hp, &h, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
-                                                     TQR_FLAG_SCOPE)) {
-                // the pusher reserves a slot before it publishes the task id,
-                // so the slot may still read -1 for a moment
-                int32_t *slot = &s.queue[lvl * s.cap + h];
-                int32_t v;
-                uint32_t spins = 0;
-                while ((v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, TQR_FLAG_SCOPE)) < 0) {
-                    // two independent bounds: the clock, and an iteration cap
-                    // that ends the wait even if the clock were not advancing
-                    if (rt_clock() > deadline || ++spins > kMaxSpins) {
-                        set_status(s, TQR_EABORTED);
-                        return -2;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                return v;
-            }
+// Waits for the highest-priority ready task.  Returns its id, or -1 when the
+// graph is finished, aborted, or the deadline passes (then the status is set).
+// An idle worker polls three words of one block (epoch, done, status) with
+// exponential back-off, and reads the queue heads and tails only when the
+// epoch shows that something was published since its last look.
+__device__ int32_t wait_for_task(const Sched &s, const volatile int32_t *abort_flag, uint64_t deadline) {
+    uint32_t spins = 0, seen = 0xffffffffu, backoff = 1;
+    for (;;) {
+        const uint32_t epoch = flag_load(&s.st->epoch);
+        const uint32_t done = flag_load(&s.st->done);
+        const int32_t status = flag_load(&s.st->status);
+        if (done >= (uint32_t)s.ntasks || status != 0) return -1;
+        if (abort_flag && flag_load(const_cast<const int32_t *>(abort_flag))) {
+            set_status(s, TQR_EABORTED);
+            return -1;
         }
+        if (epoch != seen) {
+            uint32_t hd[kLevels], tl[kLevels];
+#pragma unroll
+            for (int l = 0; l < kLevels; ++l) {
+                hd[l] = flag_load(&s.st->head[l]);
+                tl[l] = flag_load(&s.st->tail[l]);
+            }
+            bool raced = false;
+#pragma unroll
+            for (int l = 0; l < kLevels; ++l) {
+                if (raced || hd[l] >= tl[l]) continue;
+                uint32_t h = hd[l];
+                if (__hip_atomic_compare_exchange_strong(&s.st->head[l], &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         TQR_FLAG_SCOPE)) {
+                    // the pusher reserves a slot before it publishes the task
+                    // id, so the slot may still read -1 for a moment
+                    const int32_t *slot = &s.queue[l * s.cap + h];
+                    int32_t v;
+                    while ((v = flag_load(slot)) < 0) {
+                        if (rt_clock() > deadline || ++spins > kMaxSpins) {
+                            set_status(s, TQR_EABORTED);
+                            return -1;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    return v;
+                }
+                raced = true;  // another worker took it: look again at once
+            }
+            if (raced) continue;
+            seen = epoch;
+            backoff = 1;
+        }
+        if (rt_clock() > deadline || ++spins > kMaxSpins) {
+            set_status(s, TQR_EABORTED);
+            return -1;
+        }
+        for (uint32_t i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(8);
+        backoff = backoff < 32 ? 2 * backoff : 32;
     }
-    return -1;
 }
 
 __device__ __forceinline__ int xcc_id() {
@@ -176,6 +222,18 @@ __device__ __forceinline__ int xcc_id() {
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
     return v & 0xf;
 }
+
+// The hardware slot register of the wave (CU, shader array and engine ids).
+__device__ __forceinline__ int hw_id() {
+    int v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(v));
+    return v;
+}
+
+// Per-task trace record: taken, acquired, body done, released (device
+// constant-rate clock), workgroup, XCD, hardware slot register, one spare.
+constexpr int kTraceFields = 8;
+
 
 struct RunOpts {
     int64_t *trace;
@@ -191,7 +249,8 @@ template <int B, int IB>
 struct TileKernels {
     static constexpr int NB = B / IB;
     static constexpr int WCOLS = 16 * NWAVES;              // columns per workgroup pass
-    static constexpr int LDP = IB + B + 1;                  // panel leading dimension
+    static constexpr int LDP = IB + B + 1;                  // panel leading dimension (odd: LDS banks)
+    static constexpr int LDV = B + 1;                       // staged V leading dimension
     static constexpr size_t PANEL_DOUBLES = (size_t)LDP * IB;
     static constexpr size_t LDS_BYTES = (PANEL_DOUBLES + 2 * IB * IB + 2 * IB + NWAVES) * sizeof(double);
 
@@ -208,8 +267,8 @@ struct TileKernels {
     };
 
     // DGEQT2 (GEQRT): A_kk <- V_kk, R_kk; T_kk written; Vkk receives V_kk as
-    // a dense unit-lower matrix for the mask-free updates.
-    __device__ static void geqrt(double *Akk, double *Tkk, double *Vkk, double *smem) {
+    // a dense unit-lower matrix for the LARFB tasks.
+    __device__ __forceinline__ static void geqrt(double *Akk, double *Tkk, double *Vkk, double *smem) {
         Lds L(smem);
         const int tid = threadIdx.x;
 #pragma unroll 1
@@ -233,11 +292,17 @@ struct TileKernels {
             }
             for (int idx = tid; idx < IB * IB; idx += NT) Tkk[(size_t)c0 * IB + idx] = L.Ts[idx];
             __syncthreads();
-            // trailing columns c0+IB..B-1 of the tile: I - V T^T V^T
+            // the panel in LDS becomes the dense unit-lower V of this block
+            for (int idx = tid; idx < IB * IB; idx += NT) {
+                const int r = idx % IB, c = idx / IB;
+                if (r <= c) L.P[(size_t)c * LDP + r] = (r == c) ? 1.0 : 0.0;
+            }
+            __syncthreads();
+            // trailing columns c0+IB..B-1: I - V T^T V^T (V row r of the tile at P row r - c0)
             for (int col0 = c0 + IB + 16 * wave_id(); col0 < B; col0 += WCOLS) {
                 Strip<B> C;
                 strip_load<B>(C, Akk + (size_t)col0 * B, B);
-                ul_block<B, IB, true>(C, Vkk, Tkk, c0);
+                panel_update<B, IB, true, false>(C, nullptr, L.P - c0, LDP, L.Ts, c0);
                 strip_store<B>(C, Akk + (size_t)col0 * B, B, c0 / 16);
             }
             __syncthreads();
@@ -246,7 +311,7 @@ struct TileKernels {
 
     // DTSQT2 (TSQRT): [R_kk; A_ik] <- R~_kk, V_ik; T_ik written.  Only the
     // upper triangle of the diagonal tile is read or written.
-    __device__ static void tsqrt(double *Akk, double *Aik, double *Tik, double *smem) {
+    __device__ __forceinline__ static void tsqrt(double *Akk, double *Aik, double *Tik, double *smem) {
         Lds L(smem);
         const int tid = threadIdx.x;
         constexpr int hp = IB + B;
@@ -274,47 +339,73 @@ struct TileKernels {
                 Aik[(size_t)(c0 + c) * B + r] = L.P[(size_t)c * LDP + IB + r];
             }
             __syncthreads();
+            // trailing columns: V_ik of this block is rows IB.. of the panel in LDS
             for (int col0 = c0 + IB + 16 * wave_id(); col0 < B; col0 += WCOLS) {
                 Strip<B> C;
                 strip_load<B>(C, Aik + (size_t)col0 * B, B);
-                ts_block<B, IB, true>(C, Akk + (size_t)col0 * B, Aik, Tik, c0);
+                panel_update<B, IB, true, true>(C, Akk + (size_t)col0 * B, L.P + IB, LDP, L.Ts, c0);
                 strip_store<B>(C, Aik + (size_t)col0 * B, B);
             }
             __syncthreads();
         }
     }
 
-    // DLARFB (LARFB) on columns [cbeg, cend) of a b-row tile C with the
-    // reflectors of diagonal tile (V_kk as a dense unit-lower matrix, T_kk):
-    // C <- Q_kk^T C (trans) or Q_kk C.
-    template <bool TRANS>
-    __device__ static void larfb(const double *Akk, const double *Tkk, double *Cb, int cbeg, int cend) {
-        for (int col0 = cbeg + 16 * wave_id(); col0 < cend; col0 += WCOLS) {
-            Strip<B> C;
-            strip_load<B>(C, Cb + (size_t)col0 * B, B);
-#pragma unroll 1
-            for (int s = 0; s < NB; ++s) {
-                const int c0 = (TRANS ? s : NB - 1 - s) * IB;
-                ul_block<B, IB, TRANS>(C, Akk, Tkk, c0);
-            }
-            strip_store<B>(C, Cb + (size_t)col0 * B, B);
+    // Stage block c0 of a reflector tile (B x IB, column-major, ld B) and its T
+    // (IB x IB) in LDS.
+    __device__ __forceinline__ static void stage(const double *V, const double *T, int c0, double *Vl, double *Tl) {
+        const int tid = threadIdx.x;
+        for (int idx = tid; idx < B * IB; idx += NT) {
+            const int r = idx % B, c = idx / B;
+            Vl[c * LDV + r] = V[(size_t)(c0 + c) * B + r];
         }
+        for (int idx = tid; idx < IB * IB; idx += NT) Tl[idx] = T[(size_t)c0 * IB + idx];
+    }
+
+    // DLARFB (LARFB) on columns [cbeg, cend) of a b-row tile with the
+    // reflectors of a diagonal tile (Vd: V_kk as a dense unit-lower matrix,
+    // T_kk): C <- Q_kk^T C (trans) or Q_kk C.
+    template <bool TRANS>
+    __device__ __forceinline__ static void larfb(const double *Vd, const double *Tkk, double *Cb, int cbeg, int cend, double *smem) {
+        double *Vl = smem, *Tl = smem + (size_t)LDV * IB;
+        // every wave works on a valid strip (waves past the end repeat the last
+        // one) so that the strip's registers have a single definition; only
+        // the owning wave stores
+        const int want = cbeg + 16 * wave_id();
+        const int col0 = min(want, cend - 16);
+        const bool owner = want < cend;
+        Strip<B> C;
+        strip_load<B>(C, Cb + (size_t)col0 * B, B);
+#pragma unroll 1
+        for (int si = 0; si < NB; ++si) {
+            const int c0 = (TRANS ? si : NB - 1 - si) * IB;
+            __syncthreads();
+            stage(Vd, Tkk, c0, Vl, Tl);
+            __syncthreads();
+            panel_update<B, IB, TRANS, false>(C, nullptr, Vl, LDV, Tl, c0);
+        }
+        if (owner) strip_store<B>(C, Cb + (size_t)col0 * B, B);
     }
 
     // DSSRFB (SSRFB) on columns [cbeg, cend) of the pair (top, C) with the
     // reflectors (V_ik, T_ik) of a TSQRT tile.
     template <bool TRANS>
-    __device__ static void ssrfb(double *Top, double *Cb, const double *Vik, const double *Tik, int cbeg, int cend) {
-        for (int col0 = cbeg + 16 * wave_id(); col0 < cend; col0 += WCOLS) {
-            Strip<B> C;
-            strip_load<B>(C, Cb + (size_t)col0 * B, B);
+    __device__ __forceinline__ static void ssrfb(double *Top, double *Cb, const double *Vik, const double *Tik, int cbeg, int cend,
+                                 double *smem) {
+        double *Vl = smem, *Tl = smem + (size_t)LDV * IB;
+        const int want = cbeg + 16 * wave_id();
+        const int col0 = min(want, cend - 16);
+        const bool owner = want < cend;
+        Strip<B> C;
+        strip_load<B>(C, Cb + (size_t)col0 * B, B);
 #pragma unroll 1
-            for (int s = 0; s < NB; ++s) {
-                const int c0 = (TRANS ? s : NB - 1 - s) * IB;
-                ts_block<B, IB, TRANS>(C, Top + (size_t)col0 * B, Vik, Tik, c0);
-            }
-            strip_store<B>(C, Cb + (size_t)col0 * B, B);
+        for (int si = 0; si < NB; ++si) {
+            const int c0 = (TRANS ? si : NB - 1 - si) * IB;
+            __syncthreads();
+            stage(Vik, Tik, c0, Vl, Tl);
+            __syncthreads();
+            panel_update<B, IB, TRANS, true>(C, Top + (size_t)col0 * B, Vl, LDV, Tl, c0, owner);
         }
+        if (owner) strip_store<B>(C, Cb + (size_t)col0 * B, B);
     }
 };
 
@@ -336,9 +427,9 @@ struct FactorBody {
         switch (t.kind) {
         case GEQRT: K::geqrt(tile(t.k, t.k), tslot(t.k, t.k), vdiag(t.k), smem); break;
         case TSQRT: K::tsqrt(tile(t.k, t.k), tile(t.i, t.k), tslot(t.i, t.k), smem); break;
-        case LARFB: K::template larfb<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend); break;
+        case LARFB: K::template larfb<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem); break;
         default:
-            K::template ssrfb<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend);
+            K::template ssrfb<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend, smem);
             break;
         }
     }
@@ -356,12 +447,12 @@ struct ApplyBody {
     __device__ const double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
     __device__ const double *tslot(int i, int k) const { return T + ((int64_t)k * p + i) * IB * B; }
     __device__ double *btile(int i) const { return Bt + (int64_t)i * B * wb; }
-    __device__ void run(const Task &t, double *) const {
+    __device__ void run(const Task &t, double *smem) const {
         const int cbeg = t.c * kStripCols, cend = min(wb, cbeg + kStripCols);
         if (t.i == t.k)
-            K::template larfb<TRANS>(Vd + (int64_t)t.k * B * B, tslot(t.k, t.k), btile(t.k), cbeg, cend);
+            K::template larfb<TRANS>(Vd + (int64_t)t.k * B * B, tslot(t.k, t.k), btile(t.k), cbeg, cend, smem);
         else
-            K::template ssrfb<TRANS>(btile(t.k), btile(t.i), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend);
+            K::template ssrfb<TRANS>(btile(t.k), btile(t.i), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend, smem);
     }
 };
 
@@ -455,47 +546,39 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
     bool retire = false;
     for (;;) {
         if (tid == 0) {
-            if (retire) __hip_atomic_fetch_add(&s.st->done, 1u, __ATOMIC_RELEASE, TQR_FLAG_SCOPE);
-            int32_t t = -1;
-            const uint64_t deadline = rt_clock() + (uint64_t)o.timeout;
-            uint32_t spins = 0;
-            for (;;) {
-                if (__hip_atomic_load(&s.st->done, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) >= (uint32_t)s.ntasks) break;
-                if (__hip_atomic_load(&s.st->status, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) != 0) break;
-                if (o.abort_flag && __hip_atomic_load(const_cast<int32_t *>(o.abort_flag), __ATOMIC_RELAXED, TQR_FLAG_SCOPE)) {
-                    set_status(s, TQR_EABORTED);
-                    break;
-                }
-                t = try_pop(s, deadline);
-                if (t >= 0) break;
-                if (t == -2 || rt_clock() > deadline || ++spins > kMaxSpins) {
-                    set_status(s, TQR_EABORTED);
-                    t = -1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-            s_task = t;
+            if (retire) __hip_atomic_fetch_add(&s.st->done, 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+            s_task = wait_for_task(s, o.abort_flag, rt_clock() + (uint64_t)o.timeout);
         }
         __syncthreads();
         const int32_t t = __builtin_amdgcn_readfirstlane(s_task);
         if (t < 0) break;
+        const uint64_t t_pop = o.trace ? rt_clock() : 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const Task task = g.decode(t);
-        if (o.trace && tid == 0) {
-            o.trace[4 * (int64_t)t + 0] = (int64_t)rt_clock();
-            o.trace[4 * (int64_t)t + 2] = blockIdx.x;
-            o.trace[4 * (int64_t)t + 3] = xcc_id();
-        }
+        const uint64_t t_acq = o.trace ? rt_clock() : 0;
         body.run(task, smem);
-        __threadfence();
+        const uint64_t t_body = o.trace ? rt_clock() : 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (o.trace && tid == 0) o.trace[4 * (int64_t)t + 1] = (int64_t)rt_clock();
+        if (o.trace && tid == 0) {
+            int64_t *tr = o.trace + kTraceFields * (int64_t)t;
+            tr[0] = (int64_t)t_pop;
+            tr[1] = (int64_t)t_acq;
+            tr[2] = (int64_t)t_body;
+            tr[3] = (int64_t)rt_clock();
+            tr[4] = blockIdx.x;
+            tr[5] = xcc_id();
+            tr[6] = hw_id();
+        }
         const int ns = g.num_successors(task);
         for (int n = tid; n < ns; n += NT) {
             const int64_t sidx = g.successor(task, n);
-            const int32_t old = __hip_atomic_fetch_add(&s.cnt[sidx], -1, __ATOMIC_ACQ_REL, TQR_FLAG_SCOPE);
-            if (old == 1) push_task(s, level_of(g, g.decode(sidx), o.policy), sidx);
+            const int32_t old = __hip_atomic_fetch_add(&s.cnt[sidx], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+            if (old == 1) {
+                // the last predecessor publishes the task
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                push_task(s, level_of(g, g.decode(sidx), o.policy), sidx);
+            }
         }
         __syncthreads();
         retire = true;
@@ -743,9 +826,11 @@ tqr_status apply_impl(bool trans, int64_t m, int64_t n, int64_t nrhs, const doub
     ApplyGraph g(p, q, cdiv(wb, kStripCols), trans);
     tqr_status st;
     if (trans)
-        st = run_graph(g, ApplyBody<B, IB, true>{W, T, Vd, Bt, (int)p, (int)wb}, sched, 0, nullptr, stream, nullptr);
+        st = run_graph(g, ApplyBody<B, IB, true>{W, T, Vd, Bt, (int)p, (int)wb}, sched, TileKernels<B, IB>::LDS_BYTES,
+                       nullptr, stream, nullptr);
     else
-        st = run_graph(g, ApplyBody<B, IB, false>{W, T, Vd, Bt, (int)p, (int)wb}, sched, 0, nullptr, stream, nullptr);
+        st = run_graph(g, ApplyBody<B, IB, false>{W, T, Vd, Bt, (int)p, (int)wb}, sched, TileKernels<B, IB>::LDS_BYTES,
+                       nullptr, stream, nullptr);
     return st;
 }
 

@@ -87,123 +87,76 @@ __device__ __forceinline__ void strip_store(const Strip<B> &s, double *col0, int
         if (rb >= rb0) st4s(p + 16 * rb, 4, s.v[rb]);
 }
 
-// W2 = T_s^T W (trans) or T_s W for the inner block starting at tile column
-// c0; T is the ib x b slot (ld = IB) of the block's reflectors.
-template <int IB, bool TRANS>
-__device__ __forceinline__ void apply_t(d4 (&W2)[IB / 16], const d4 (&W)[IB / 16], const double *T, int c0) {
+// One wave applies the block reflector of one inner block (IB columns) to its
+// 16-column strip C (all B rows, in registers).  V and T come from LDS:
+//   V(row, a) = Vl[a * ldv + row]  for the block's column a (0..IB-1) and the
+//               tile row `row`; T(r, c) = Tl[c * IB + r].
+// TS (the TSQRT/SSRFB form, reflectors [I; V]):
+//   W = top[c0:c0+IB] + V^T C,  W = op(T) W,  top[c0:c0+IB] -= W,  C -= V W
+//   with `top` column 0 of the strip in the upper tile (global, ld B).
+// !TS (the GEQRT/LARFB form, V dense unit lower, zero above row c0):
+//   W = V^T C,  W = op(T) W,  C -= V W, over rows c0..B-1 only.
+// op(T) = T^T applies Q^T (factorisation); T applies Q.  A wave that only
+// duplicates another wave's columns passes write_top = false.
+template <int B, int IB, bool TRANS, bool TS>
+__device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const double *Vl, int ldv, const double *Tl,
+                                             int c0, bool write_top = true) {
     constexpr int NA = IB / 16;
     const int l = lane_id();
+    const int rb0 = TS ? 0 : c0 / 16;
+    d4 W[NA], W2[NA];
+    double *tp = TS ? top + (size_t)(l & 15) * B + c0 + (l >> 4) : nullptr;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) W[a] = TS ? ld4s(tp + 16 * a, 4) : d4{0.0, 0.0, 0.0, 0.0};
+    // k-slice (rb, r): rows 16rb + 4r + {0..3}; A operand V^T[16a + l%16][16rb + 4r + l/16]
+    const double *vp = Vl + (l & 15) * ldv + (l >> 4);
+#pragma unroll
+    for (int rb = 0; rb < B / 16; ++rb) {
+        if (!TS && rb < rb0) continue;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const double *q = vp + 16 * a * ldv + 16 * rb;
+            W[a] = mfma(q[0], C.v[rb].x, W[a]);
+            W[a] = mfma(q[4], C.v[rb].y, W[a]);
+            W[a] = mfma(q[8], C.v[rb].z, W[a]);
+            W[a] = mfma(q[12], C.v[rb].w, W[a]);
+        }
+        sched_fence();
+    }
+    // W2 = op(T) W; A operand of k-slice (a, r): op(T)[16o + l%16][16a + 4r + l/16]
 #pragma unroll
     for (int o = 0; o < NA; ++o) W2[o] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int o = 0; o < NA; ++o) {
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
-            if (TRANS ? (a > o) : (a < o)) continue;  // T upper triangular
-            // A operand of k-slice r: lane l needs op(T)[16o + l%16][16a + 4r + l/16]
-            const d4 t = TRANS ? ld4s(T + (size_t)(c0 + 16 * o + (l & 15)) * IB + 16 * a + (l >> 4), 4)
-                               : ld4s(T + (size_t)(c0 + 16 * a + (l >> 4)) * IB + 16 * o + (l & 15), 4 * IB);
-            W2[o] = mfma(t.x, W[a].x, W2[o]);
-            W2[o] = mfma(t.y, W[a].y, W2[o]);
-            W2[o] = mfma(t.z, W[a].z, W2[o]);
-            W2[o] = mfma(t.w, W[a].w, W2[o]);
+            if (TRANS ? (a > o) : (a < o)) continue;  // T is upper triangular
+            const double *tq = TRANS ? Tl + (16 * o + (l & 15)) * IB + 16 * a + (l >> 4)
+                                     : Tl + (16 * a + (l >> 4)) * IB + 16 * o + (l & 15);
+            const int st = TRANS ? 4 : 4 * IB;
+            W2[o] = mfma(tq[0], W[a].x, W2[o]);
+            W2[o] = mfma(tq[st], W[a].y, W2[o]);
+            W2[o] = mfma(tq[2 * st], W[a].z, W2[o]);
+            W2[o] = mfma(tq[3 * st], W[a].w, W2[o]);
         }
     }
-}
-
-// Apply the block reflector of inner block c0..c0+IB-1 of a TSQRT tile,
-// I - [I; V] op(T) [I; V]^T, to the pair [top rows c0..c0+IB-1; C]:
-//   W = top[c0:c0+IB] + V^T C,  W = op(T) W,  top[c0:c0+IB] -= W,  C -= V W.
-// op(T) = T^T applies Q^T (factorisation), T applies Q.
-//   C    : strip of the lower tile in registers (all B rows)
-//   top  : column 0 of the same strip in the upper tile (global, ld B)
-//   V    : the V_ik tile (global, full B x B), T its slot.
-template <int B, int IB, bool TRANS>
-__device__ __forceinline__ void ts_block(Strip<B> &C, double *top, const double *V, const double *T, int c0) {
-    constexpr int NA = IB / 16;
-    const int l = lane_id();
-    d4 W[NA], W2[NA];
-    double *tp = top + (size_t)(l & 15) * B + c0 + (l >> 4);
-#pragma unroll
-    for (int a = 0; a < NA; ++a) W[a] = ld4s(tp + 16 * a, 4);
-    // A operand of k-slice (rb, r): V^T[16a + l%16][16rb + 4r + l/16]
-    const double *vp = V + (size_t)(c0 + (l & 15)) * B + (l >> 4);
-#pragma unroll
-    for (int rb = 0; rb < B / 16; ++rb) {
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            const d4 v = ld4s(vp + (size_t)16 * a * B + 16 * rb, 4);
-            W[a] = mfma(v.x, C.v[rb].x, W[a]);
-            W[a] = mfma(v.y, C.v[rb].y, W[a]);
-            W[a] = mfma(v.z, C.v[rb].z, W[a]);
-            W[a] = mfma(v.w, C.v[rb].w, W[a]);
-        }
-        sched_fence();
-    }
-    apply_t<IB, TRANS>(W2, W, T, c0);
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
-        st4s(tp + 16 * a, 4, ld4s(tp + 16 * a, 4) - W2[a]);
+        if (TS && write_top) st4s(tp + 16 * a, 4, ld4s(tp + 16 * a, 4) - W2[a]);
         W2[a] = -W2[a];
     }
-    // A operand of k-slice (a, r): V[16rb + l%16][c0 + 16a + 4r + l/16]
-    const double *vq = V + (size_t)(c0 + (l >> 4)) * B + (l & 15);
+    // C -= V W2; A operand of k-slice (a, r): V[16rb + l%16][16a + 4r + l/16]
+    const double *vq = Vl + (l >> 4) * ldv + (l & 15);
 #pragma unroll
     for (int rb = 0; rb < B / 16; ++rb) {
+        if (!TS && rb < rb0) continue;
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
-            const double *q = vq + (size_t)16 * a * B + 16 * rb;
+            const double *q = vq + 16 * a * ldv + 16 * rb;
             C.v[rb] = mfma(q[0], W2[a].x, C.v[rb]);
-            C.v[rb] = mfma(q[4 * B], W2[a].y, C.v[rb]);
-            C.v[rb] = mfma(q[8 * B], W2[a].z, C.v[rb]);
-            C.v[rb] = mfma(q[12 * B], W2[a].w, C.v[rb]);
-        }
-        sched_fence();
-    }
-}
-
-// Apply the block reflector of inner block c0..c0+IB-1 of a GEQRT tile,
-// I - V op(T) V^T, to rows c0..B-1 of C:
-//   W = V^T C,  W = op(T) W,  C -= V W.
-// V is the diagonal tile's reflectors written out as a dense unit-lower
-// B x B matrix (exact zeros above the diagonal, ones on it), so the update
-// needs no masking; rows above c0 are zero in V and are skipped.
-template <int B, int IB, bool TRANS, bool SKIP = false>
-__device__ __forceinline__ void ul_block(Strip<B> &C, const double *V, const double *T, int c0) {
-    constexpr int NA = IB / 16;
-    const int l = lane_id();
-    const int rb0 = c0 / 16;
-    d4 W[NA], W2[NA];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) W[a] = d4{0.0, 0.0, 0.0, 0.0};
-    const double *vp = V + (size_t)(c0 + (l & 15)) * B + (l >> 4);
-#pragma unroll
-    for (int rb = 0; rb < B / 16; ++rb) {
-        if (SKIP && rb < rb0) continue;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            const d4 v = ld4s(vp + (size_t)16 * a * B + 16 * rb, 4);
-            W[a] = mfma(v.x, C.v[rb].x, W[a]);
-            W[a] = mfma(v.y, C.v[rb].y, W[a]);
-            W[a] = mfma(v.z, C.v[rb].z, W[a]);
-            W[a] = mfma(v.w, C.v[rb].w, W[a]);
-        }
-        sched_fence();
-    }
-    apply_t<IB, TRANS>(W2, W, T, c0);
-#pragma unroll
-    for (int a = 0; a < NA; ++a) W2[a] = -W2[a];
-    const double *vq = V + (size_t)(c0 + (l >> 4)) * B + (l & 15);
-#pragma unroll
-    for (int rb = 0; rb < B / 16; ++rb) {
-        if (SKIP && rb < rb0) continue;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            const double *q = vq + (size_t)16 * a * B + 16 * rb;
-            C.v[rb] = mfma(q[0], W2[a].x, C.v[rb]);
-            C.v[rb] = mfma(q[4 * B], W2[a].y, C.v[rb]);
-            C.v[rb] = mfma(q[8 * B], W2[a].z, C.v[rb]);
-            C.v[rb] = mfma(q[12 * B], W2[a].w, C.v[rb]);
+            C.v[rb] = mfma(q[4 * ldv], W2[a].y, C.v[rb]);
+            C.v[rb] = mfma(q[8 * ldv], W2[a].z, C.v[rb]);
+            C.v[rb] = mfma(q[12 * ldv], W2[a].w, C.v[rb]);
         }
         sched_fence();
     }

@@ -137,11 +137,12 @@ def test_trace_respects_the_task_graph():
     _say("case trace 384x384 b=64")
     p = q = m // b
     nt = tqr.graph_tasks(p, q, b)
-    trace = torch.zeros(4 * nt, dtype=torch.int64, device="cuda")
+    trace = torch.zeros(8 * nt, dtype=torch.int64, device="cuda")
     run_factor(workloads.gaussian(m, n, seed=6), b, 16, trace=trace)
-    tr = trace.cpu().numpy().reshape(nt, 4)
-    start, end = tr[:, 0], tr[:, 1]
+    tr = trace.cpu().numpy().reshape(nt, 8)
+    start, end = tr[:, 0], tr[:, 3]
     assert np.all(end >= start) and np.all(start > 0)
+    assert np.all(tr[:, 1] >= tr[:, 0]) and np.all(tr[:, 2] >= tr[:, 1]) and np.all(tr[:, 3] >= tr[:, 2])
     for u in range(nt):
         for v in tqr.graph_successors(p, q, b, u):
             assert start[v] >= end[u], (tqr.graph_task(p, q, b, u), tqr.graph_task(p, q, b, v))
