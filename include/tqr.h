@@ -93,7 +93,9 @@ typedef struct tqr_options {
     int64_t *trace;            /* device, 8 int64 per task or NULL: taken, acquired,
                                   body done, released (device constant-rate clock
                                   ticks), workgroup, XCD, the wave's
-                                  HW_ID register (CU/SE ids), 0 */
+                                  HW_ID register (CU/SE ids), and 1 if the
+                                  task ran as the continuation of the worker's
+                                  previous task (0 if taken from a queue) */
     const volatile int32_t *abort_flag; /* host-mapped or device int polled while
                                            waiting for work; nonzero aborts; or NULL */
     int32_t *status;           /* device int or NULL: 0 done, TQR_EABORTED */

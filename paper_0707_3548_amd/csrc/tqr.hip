@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -50,60 +51,72 @@ __global__ void k_tiles_to_cm(const double *__restrict__ W, int p, int b, int tw
 // ===========================================================================
 // Scheduler state (in the caller's workspace)
 // ===========================================================================
-// The words that idle workers poll (epoch, done, status), the queue heads and
-// the queue tails each sit in their own 256-byte block, so that polling and
-// the atomics of busy workers do not queue behind each other.
+// Hot words are grouped by who touches them, each group in its own 256-byte
+// block: the done count and status; the queue words; the idle-worker bitmap.
+// Every worker also owns a mailbox on a 128-byte line of its own, the only
+// word it polls while idle.
+constexpr int kMaxWorkers = 2048;      // persistent workgroups per launch, at most
+constexpr int kMboxStride = 32;        // ints between mailboxes
+constexpr int32_t kMboxEmpty = -1;     // mailbox values; task ids are >= 0
+constexpr int32_t kMboxWake = -2;      // look at the ready queues again
+constexpr int32_t kMboxStop = -3;      // the graph is finished or aborted: exit
+
 struct SchedState {
-    uint32_t epoch;   // number of tasks published so far
-    uint32_t done;    // number of tasks finished
+    uint32_t pad_a;
+    uint32_t done;    // number of finished tasks without successors
     int32_t status;   // 0, or TQR_EABORTED
-    uint32_t pad0[61];
-    uint32_t head[8];
-    uint32_t pad1[56];
-    uint32_t tail[8];
-    uint32_t pad2[56];
+    uint32_t nsinks;  // number of tasks without successors (set by k_sched_seed)
+    uint32_t pad0[60];
+    uint64_t ht[8];   // per priority level: (tail << 32) | head of its queue
+    uint32_t pad1[48];
+    uint64_t idle[kMaxWorkers / 64];  // bit w set: worker w waits on its mailbox
 };
 static_assert(sizeof(SchedState) == 768, "state layout");
+static_assert(offsetof(SchedState, ht) == 256 && offsetof(SchedState, idle) == 512, "hot words in their own blocks");
 
 struct Sched {
     SchedState *st;
+    int32_t *mbox;    // kMaxWorkers mailboxes, kMboxStride ints apart
     int32_t *cnt;     // remaining in-degree per task
     int32_t *queue;   // kLevels arrays of `cap` task ids, -1 = not yet written
     int64_t cap;      // = number of tasks
     int64_t ntasks;
 };
 
+constexpr int64_t kMboxBytes = (int64_t)kMaxWorkers * kMboxStride * 4;
+
 __host__ __device__ inline int64_t sched_bytes(int64_t ntasks) {
-    return (int64_t)sizeof(SchedState) + ((ntasks * 4 * (1 + kLevels) + 255) / 256) * 256;
+    return (int64_t)sizeof(SchedState) + kMboxBytes + ((ntasks * 4 * (1 + kLevels) + 255) / 256) * 256;
 }
 
 __host__ inline Sched sched_at(void *base, int64_t ntasks) {
     Sched s;
-    s.st = reinterpret_cast<SchedState *>(base);
-    s.cnt = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(base) + sizeof(SchedState));
+    char *c = reinterpret_cast<char *>(base);
+    s.st = reinterpret_cast<SchedState *>(c);
+    s.mbox = reinterpret_cast<int32_t *>(c + sizeof(SchedState));
+    s.cnt = reinterpret_cast<int32_t *>(c + sizeof(SchedState) + kMboxBytes);
     s.queue = s.cnt + ntasks;
     s.cap = ntasks;
     s.ntasks = ntasks;
     return s;
 }
 
+// Grid: max(ntasks, kMaxWorkers) threads.
 template <class G>
-__global__ void k_sched_init(G g, Sched s, int policy, int64_t src0, int64_t src1) {
+__global__ void k_sched_init(G g, Sched s) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < s.ntasks) {
         s.cnt[t] = g.indegree(g.decode(t));
         for (int l = 0; l < kLevels; ++l) s.queue[l * s.cap + t] = -1;
     }
+    if (t < kMaxWorkers) s.mbox[t * kMboxStride] = kMboxEmpty;
+    if (t < kMaxWorkers / 64) s.st->idle[t] = 0;
     if (t == 0) {
-        for (int l = 0; l < 8; ++l) {
-            s.st->head[l] = 0;
-            s.st->tail[l] = 0;
-        }
-        s.st->epoch = 0;
+        for (int l = 0; l < 8; ++l) s.st->ht[l] = 0;
         s.st->done = 0;
         s.st->status = 0;
+        s.st->nsinks = 0;
     }
-    (void)policy; (void)src0; (void)src1;
 }
 
 template <class G>
@@ -117,27 +130,14 @@ __device__ __host__ inline int level_of<TrsmGraph>(const TrsmGraph &, const Task
     return t.kind == 0 ? 0 : 1;
 }
 
-// Pushes the tasks without predecessors.  Runs as its own launch after
-// k_sched_init, so every slot is already cleared.
-template <class G>
-__global__ void k_sched_seed(G g, Sched s, int policy) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= s.ntasks) return;
-    const Task task = g.decode(t);
-    if (g.indegree(task) != 0) return;
-    const int lvl = level_of(g, task, policy);
-    const uint32_t pos = __hip_atomic_fetch_add(&s.st->tail[lvl], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&s.queue[lvl * s.cap + pos], (int32_t)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_fetch_add(&s.st->epoch, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-// Scheduler flags (queue heads and tails, slots, dependency counters, the done
-// count and the status) are accessed with relaxed system-scope atomics: a
-// system-scope access is never served from one XCD's L2, so a flag written on
-// one XCD is seen on every other.  Tile data is ordered by explicit fences: a
-// task releases its writes (agent-scope release fence) before it decrements
-// its successors' counters, and a worker acquires (agent-scope acquire fence)
-// after it takes a task.
+// Scheduler words (queue words and slots, dependency counters, the idle
+// bitmap, mailboxes, the done count and the status) are accessed with relaxed
+// system-scope atomics, which no XCD serves from a stale copy in its own L2.
+// Tile data is ordered by explicit fences: a task releases its writes
+// (agent-scope release fence) before it decrements its successors' counters;
+// the worker that finds a task ready acquires the other predecessors' writes
+// and releases them onward (acquire-release fence) before it publishes the
+// task; a worker acquires (agent-scope acquire fence) after it takes a task.
 #define TQR_FLAG_SCOPE __HIP_MEMORY_SCOPE_SYSTEM
 
 __device__ __forceinline__ uint64_t rt_clock() { return wall_clock64(); }
@@ -147,73 +147,151 @@ __device__ __forceinline__ T flag_load(const T *p) {
     return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
 }
 
-__device__ __forceinline__ void push_task(const Sched &s, int lvl, int64_t t) {
-    const uint32_t pos = __hip_atomic_fetch_add(&s.st->tail[lvl], 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
-    __hip_atomic_store(&s.queue[lvl * s.cap + pos], (int32_t)t, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
-    __hip_atomic_fetch_add(&s.st->epoch, 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
-}
-
 __device__ __forceinline__ void set_status(const Sched &s, int32_t v) {
     __hip_atomic_store(&s.st->status, v, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
 }
 
+// Pushes the tasks without predecessors and counts the tasks without
+// successors.  Runs as its own launch after k_sched_init, so every slot and
+// count is already cleared; the persistent launch comes after it.
+template <class G>
+__global__ void k_sched_seed(G g, Sched s, int policy) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s.ntasks) return;
+    const Task task = g.decode(t);
+    if (g.num_successors(task) == 0) __hip_atomic_fetch_add(&s.st->nsinks, 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+    if (g.indegree(task) != 0) return;
+    const int lvl = level_of(g, task, policy);
+    const uint32_t pos = (uint32_t)(__hip_atomic_fetch_add(&s.st->ht[lvl], 1ull << 32, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) >> 32);
+    __hip_atomic_store(&s.queue[lvl * s.cap + pos], (int32_t)t, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+}
+
 constexpr uint32_t kMaxSpins = 1u << 26;  // a second bound on every wait, independent of the clock
 
-// Waits for the highest-priority ready task.  Returns its id, or -1 when the
-// graph is finished, aborted, or the deadline passes (then the status is set).
-// An idle worker polls three words of one block (epoch, done, status) with
-// exponential back-off, and reads the queue heads and tails only when the
-// epoch shows that something was published since its last look.
-__device__ int32_t wait_for_task(const Sched &s, const volatile int32_t *abort_flag, uint64_t deadline) {
-    uint32_t spins = 0, seen = 0xffffffffu, backoff = 1;
-    for (;;) {
-        const uint32_t epoch = flag_load(&s.st->epoch);
-        const uint32_t done = flag_load(&s.st->done);
-        const int32_t status = flag_load(&s.st->status);
-        if (done >= (uint32_t)s.ntasks || status != 0) return -1;
-        if (abort_flag && flag_load(const_cast<const int32_t *>(abort_flag))) {
-            set_status(s, TQR_EABORTED);
-            return -1;
-        }
-        if (epoch != seen) {
-            uint32_t hd[kLevels], tl[kLevels];
+// Writes kMboxStop into every worker's mailbox.
+__device__ void broadcast_stop(const Sched &s, int nworkers) {
+    for (int w = 0; w < nworkers; ++w)
+        __hip_atomic_store(&s.mbox[w * kMboxStride], kMboxStop, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+}
+
+__device__ void abort_run(const Sched &s, int nworkers) {
+    set_status(s, TQR_EABORTED);
+    broadcast_stop(s, nworkers);
+}
+
+// One look at the ready queues: takes the head task of the highest-priority
+// non-empty level.  Returns the task id, -1 if every level looked empty or
+// other workers took what there was, -2 after an abort.
+__device__ int32_t try_pop(const Sched &s, uint64_t deadline, uint32_t &spins, int nworkers) {
+    uint64_t w[kLevels];
 #pragma unroll
-            for (int l = 0; l < kLevels; ++l) {
-                hd[l] = flag_load(&s.st->head[l]);
-                tl[l] = flag_load(&s.st->tail[l]);
-            }
-            bool raced = false;
-#pragma unroll
-            for (int l = 0; l < kLevels; ++l) {
-                if (raced || hd[l] >= tl[l]) continue;
-                uint32_t h = hd[l];
-                if (__hip_atomic_compare_exchange_strong(&s.st->head[l], &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                         TQR_FLAG_SCOPE)) {
-                    // the pusher reserves a slot before it publishes the task
-                    // id, so the slot may still read -1 for a moment
-                    const int32_t *slot = &s.queue[l * s.cap + h];
-                    int32_t v;
-                    while ((v = flag_load(slot)) < 0) {
-                        if (rt_clock() > deadline || ++spins > kMaxSpins) {
-                            set_status(s, TQR_EABORTED);
-                            return -1;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
+    for (int l = 0; l < kLevels; ++l) w[l] = flag_load(&s.st->ht[l]);
+    for (int l = 0; l < kLevels; ++l) {
+        uint64_t cur = w[l];
+        // a failed exchange returns the current word: retry at once while
+        // the level still holds work (a push also changes the word)
+        for (int tries = 0; tries < 4 && (uint32_t)cur < (uint32_t)(cur >> 32); ++tries) {
+            if (__hip_atomic_compare_exchange_strong(&s.st->ht[l], &cur, cur + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     TQR_FLAG_SCOPE)) {
+                // the pusher reserves a slot before it writes the task id, so
+                // the slot may still read -1 for a moment
+                const int32_t *slot = &s.queue[l * s.cap + (uint32_t)cur];
+                int32_t v;
+                while ((v = flag_load(slot)) < 0) {
+                    if (rt_clock() > deadline || ++spins > kMaxSpins) {
+                        abort_run(s, nworkers);
+                        return -2;
                     }
-                    return v;
+                    __builtin_amdgcn_s_sleep(1);
                 }
-                raced = true;  // another worker took it: look again at once
+                return v;
             }
-            if (raced) continue;
-            seen = epoch;
-            backoff = 1;
         }
-        if (rt_clock() > deadline || ++spins > kMaxSpins) {
-            set_status(s, TQR_EABORTED);
-            return -1;
+    }
+    return -1;
+}
+
+// Thread 0 of an idle worker: returns the next task, or -1 when the graph is
+// finished or aborted.  An idle worker sets its bit in the idle bitmap, looks
+// at the queues once more, and then polls only its own mailbox.  A worker
+// that publishes tasks pushes them first and then wakes idle workers; with a
+// sequentially consistent fence between the write and the read on both sides
+// (bit set -> queue look; push -> bitmap look), a task published while a
+// worker goes idle is seen by one of the two, so no task is left in a queue
+// while every worker waits.  Waits are bounded by the deadline and a spin
+// count; the periodic check of the done count, the status and the abort flag
+// also ends a wait.
+__device__ int32_t idle_wait(const Sched &s, uint32_t nsinks, const volatile int32_t *abort_flag, uint64_t deadline,
+                             int me, int nworkers) {
+    uint32_t spins = 0;
+    uint64_t *word = &s.st->idle[me >> 6];
+    const uint64_t bit = 1ull << (me & 63);
+    int32_t *mb = &s.mbox[me * kMboxStride];
+    for (;;) {
+        if (flag_load(&s.st->status) != 0) return -1;
+        int32_t t = try_pop(s, deadline, spins, nworkers);
+        if (t >= 0) return t;
+        if (t == -2) return -1;
+        __hip_atomic_fetch_or(word, bit, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        t = try_pop(s, deadline, spins, nworkers);
+        if (t >= 0) {
+            // withdraw; if a waker cleared the bit first, its wake-up stays
+            // in the mailbox and only costs one extra look later
+            __hip_atomic_fetch_and(word, ~bit, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+            return t;
         }
-        for (uint32_t i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(8);
-        backoff = backoff < 32 ? 2 * backoff : 32;
+        if (t == -2) return -1;
+        uint32_t polls = 0;
+        for (;;) {
+            if (flag_load(mb) != kMboxEmpty) {
+                const int32_t v = __hip_atomic_exchange(mb, kMboxEmpty, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+                if (v == kMboxStop) return -1;
+                if (v != kMboxEmpty) break;  // woken: look at the queues
+            }
+            if ((++polls & 63) == 0) {
+                if (flag_load(&s.st->done) >= nsinks || flag_load(&s.st->status) != 0) return -1;
+                if ((abort_flag && flag_load(const_cast<const int32_t *>(abort_flag))) || rt_clock() > deadline) {
+                    abort_run(s, nworkers);
+                    return -1;
+                }
+            }
+            if (++spins > kMaxSpins) {
+                abort_run(s, nworkers);
+                return -1;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+    }
+}
+
+// Thread 0 after pushing `count` tasks: wakes up to `count` idle workers.
+__device__ void wake_idle(const Sched &s, int count, int nworkers) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    const int nwords = (nworkers + 63) >> 6;
+    for (int wi = 0; wi < nwords && count > 0; ++wi) {
+        uint64_t v = flag_load(&s.st->idle[wi]);
+        while (v != 0 && count > 0) {
+            // claim up to `count` of the set bits with one exchange
+            uint64_t mask = 0, rest = v;
+            for (int c = 0; c < count && rest != 0; ++c) {
+                const uint64_t low = rest & (~rest + 1);
+                mask |= low;
+                rest &= rest - 1;
+            }
+            const uint64_t old = __hip_atomic_fetch_and(&s.st->idle[wi], ~mask, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+            uint64_t got = old & mask;
+            while (got != 0) {
+                const int w = (wi << 6) + __builtin_ctzll(got);
+                got &= got - 1;
+                int32_t expect = kMboxEmpty;
+                // never overwrite a stop
+                __hip_atomic_compare_exchange_strong(&s.mbox[w * kMboxStride], &expect, kMboxWake, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+                --count;
+            }
+            v = old & ~mask;
+        }
     }
 }
 
@@ -231,7 +309,8 @@ __device__ __forceinline__ int hw_id() {
 }
 
 // Per-task trace record: taken, acquired, body done, released (device
-// constant-rate clock), workgroup, XCD, hardware slot register, one spare.
+// constant-rate clock), workgroup, XCD, hardware slot register, and 1 when
+// the task ran as its predecessor's continuation (0 when it was popped).
 constexpr int kTraceFields = 8;
 
 
@@ -534,26 +613,54 @@ struct TrsmBody {
 // highest-priority ready task, runs it, and releases its successors; a
 // successor whose last dependency is released is pushed on its level's queue.
 // ===========================================================================
+__device__ __forceinline__ bool queue_has_level_below(const Sched &s, int lvl) {
+    for (int l = 0; l < lvl; ++l) {
+        const uint64_t w = flag_load(&s.st->ht[l]);
+        if ((uint32_t)w < (uint32_t)(w >> 32)) return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ void push_one(const Sched &s, int lvl, int32_t t) {
+    const uint32_t pos = (uint32_t)(__hip_atomic_fetch_add(&s.st->ht[lvl], 1ull << 32, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) >> 32);
+    __hip_atomic_store(&s.queue[lvl * s.cap + pos], t, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+}
+
+constexpr int kReadyCap = 64;  // ready successors collected per task before publishing
+
 template <class G, class Body>
 __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunOpts o) {
     extern __shared__ double smem[];
-    __shared__ int32_t s_task;
+    __shared__ int32_t s_task, s_cont, s_nready, s_nover;
+    __shared__ int32_t s_ready[kReadyCap];
+    __shared__ int8_t s_lvl[kReadyCap];
     const int tid = threadIdx.x;
-    // One thread-0 region per iteration: it retires the previous task (done
-    // count), then waits for the next.  The task id is made wave-uniform with
-    // readfirstlane, so the loop exit is a scalar branch and every lane of
-    // every wave meets each barrier in the same iteration.
-    bool retire = false;
+    const int nworkers = gridDim.x;
+    // Thread 0 owns the scheduling decisions: the next task is either the
+    // continuation chosen at the end of the previous task or one taken from
+    // the ready queues.  The task id is made wave-uniform with readfirstlane,
+    // so the loop exit is a scalar branch and every lane of every wave meets
+    // each barrier in the same iteration.
+    uint32_t nsinks = 0;
+    if (tid == 0) nsinks = flag_load(&s.st->nsinks);
+    int32_t next = -1;  // thread 0: continuation task or -1
     for (;;) {
         if (tid == 0) {
-            if (retire) __hip_atomic_fetch_add(&s.st->done, 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
-            s_task = wait_for_task(s, o.abort_flag, rt_clock() + (uint64_t)o.timeout);
+            if (next >= 0 && flag_load(&s.st->status) != 0) next = -1;
+            s_cont = next >= 0;
+            s_task = next >= 0 ? next
+                               : idle_wait(s, nsinks, o.abort_flag, rt_clock() + (uint64_t)o.timeout, blockIdx.x, nworkers);
+            s_nready = 0;
+            s_nover = 0;
         }
         __syncthreads();
         const int32_t t = __builtin_amdgcn_readfirstlane(s_task);
         if (t < 0) break;
+        const int cont = __builtin_amdgcn_readfirstlane(s_cont);
         const uint64_t t_pop = o.trace ? rt_clock() : 0;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // a task taken from a queue acquires its predecessors' writes here;
+        // for a continuation the thread that found it ready already did
+        if (!cont) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const Task task = g.decode(t);
         const uint64_t t_acq = o.trace ? rt_clock() : 0;
         body.run(task, smem);
@@ -569,19 +676,63 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
             tr[4] = blockIdx.x;
             tr[5] = xcc_id();
             tr[6] = hw_id();
+            tr[7] = cont;
         }
+        // Successors: the last predecessor to finish makes a task ready.
         const int ns = g.num_successors(task);
         for (int n = tid; n < ns; n += NT) {
             const int64_t sidx = g.successor(task, n);
             const int32_t old = __hip_atomic_fetch_add(&s.cnt[sidx], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
             if (old == 1) {
-                // the last predecessor publishes the task
+                // acquire the other predecessors' writes, release them onward
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-                push_task(s, level_of(g, g.decode(sidx), o.policy), sidx);
+                const int lvl = level_of(g, g.decode(sidx), o.policy);
+                const int slot = atomicAdd(&s_nready, 1);
+                if (slot < kReadyCap) {
+                    s_ready[slot] = (int32_t)sidx;
+                    s_lvl[slot] = (int8_t)lvl;
+                } else {
+                    push_one(s, lvl, (int32_t)sidx);
+                    atomicAdd(&s_nover, 1);
+                }
             }
         }
         __syncthreads();
-        retire = true;
+        if (tid == 0) {
+            next = -1;
+            if (ns == 0) {
+                const uint32_t d = __hip_atomic_fetch_add(&s.st->done, 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) + 1;
+                if (d == nsinks) broadcast_stop(s, nworkers);
+            }
+            const int nr = min(s_nready, kReadyCap);
+            // keep the highest-priority ready successor (lowest level, then
+            // lowest id) unless a queue holds work of a higher priority;
+            // publish the rest, one queue-word update per level
+            int best = -1, best_lvl = kLevels;
+            for (int r = 0; r < nr; ++r) {
+                const int lvl = s_lvl[r];
+                if (lvl < best_lvl || (lvl == best_lvl && s_ready[r] < s_ready[best])) {
+                    best = r;
+                    best_lvl = lvl;
+                }
+            }
+            if (best >= 0 && queue_has_level_below(s, best_lvl)) best = -1;
+            int pushed = s_nover;
+            for (int l = 0; l < kLevels; ++l) {
+                int c = 0;
+                for (int r = 0; r < nr; ++r) c += (r != best && s_lvl[r] == l);
+                if (c == 0) continue;
+                const uint32_t base = (uint32_t)(
+                    __hip_atomic_fetch_add(&s.st->ht[l], (uint64_t)c << 32, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) >> 32);
+                int i = 0;
+                for (int r = 0; r < nr; ++r)
+                    if (r != best && s_lvl[r] == l)
+                        __hip_atomic_store(&s.queue[l * s.cap + base + i++], s_ready[r], __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+                pushed += c;
+            }
+            if (pushed > 0) wake_idle(s, pushed, nworkers);
+            if (best >= 0) next = s_ready[best];
+        }
     }
 }
 
@@ -733,14 +884,14 @@ tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, 
         if (status_out) HIPCHK(hipMemsetAsync(status_out, 0, sizeof(int32_t), stream));
         return TQR_OK;
     }
-    const int blocks_init = (int)cdiv(nt, 256);
-    hipLaunchKernelGGL(k_sched_init<G>, dim3(blocks_init), dim3(256), 0, stream, g, s, policy, (int64_t)0, (int64_t)0);
-    hipLaunchKernelGGL(k_sched_seed<G>, dim3(blocks_init), dim3(256), 0, stream, g, s, policy);
+    const int blocks_init = (int)cdiv(std::max<int64_t>(nt, kMaxWorkers), 256);
+    hipLaunchKernelGGL(k_sched_init<G>, dim3(blocks_init), dim3(256), 0, stream, g, s);
+    hipLaunchKernelGGL(k_sched_seed<G>, dim3((unsigned)cdiv(nt, 256)), dim3(256), 0, stream, g, s, policy);
     int per_cu = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kp, NT, lds));
     int64_t workers = (int64_t)std::max(per_cu, 1) * cu_count();
     if (opt && opt->workgroups > 0) workers = std::min<int64_t>(workers, opt->workgroups);
-    workers = std::min<int64_t>(workers, nt);
+    workers = std::min<int64_t>(std::min<int64_t>(workers, nt), kMaxWorkers);
     RunOpts ro;
     ro.trace = opt ? opt->trace : nullptr;
     ro.abort_flag = opt ? opt->abort_flag : nullptr;
