@@ -331,7 +331,184 @@ struct TileKernels {
     static constexpr int LDP = IB + B + 1;                  // panel leading dimension (odd: LDS banks)
     static constexpr int LDV = B + 1;                       // staged V leading dimension
     static constexpr size_t PANEL_DOUBLES = (size_t)LDP * IB;
-    static constexpr size_t LDS_BYTES = (PANEL_DOUBLES + 2 * IB * IB + 2 * IB + NWAVES) * sizeof(double);
+    static constexpr size_t LDS_GENERIC = (PANEL_DOUBLES + 2 * IB * IB + 2 * IB + NWAVES) * sizeof(double);
+    // ib = 16 panels: two V buffers (16 x LDV), two T buffers (16 x 16), the
+    // 16 x 16 diagonal block of R for TSQRT, the one-wave panel scratch
+    static constexpr size_t LDS_IB16 = (2 * 16 * (size_t)LDV + 2 * 256 + 256 + kPanelScratch) * sizeof(double);
+    static constexpr size_t LDS_BYTES = IB == 16 && LDS_IB16 > LDS_GENERIC ? LDS_IB16 : LDS_GENERIC;
+    static constexpr int RPL = B >= 64 ? B / 64 : 1;        // panel rows per lane (one-wave panels)
+
+    // A strip (matrix-core accumulator layout) into LDS as Vl[c * LDV + r].
+    __device__ __forceinline__ static void strip_to_lds(const Strip<B> &C, double *Vl) {
+        const int l = lane_id();
+        double *p = Vl + (l & 15) * LDV + (l >> 4);
+#pragma unroll
+        for (int rb = 0; rb < B / 16; ++rb) {
+            p[16 * rb] = C.v[rb].x;
+            p[16 * rb + 4] = C.v[rb].y;
+            p[16 * rb + 8] = C.v[rb].z;
+            p[16 * rb + 12] = C.v[rb].w;
+        }
+    }
+
+    // Row block rb (rows 16rb .. 16rb+15) of a strip to global memory.
+    __device__ __forceinline__ static void strip_store_block(const Strip<B> &C, double *col0, int rb) {
+        const int l = lane_id();
+        double *p = col0 + (size_t)(l & 15) * B + (l >> 4) + 16 * rb;
+#pragma unroll
+        for (int r = 0; r < B / 16; ++r)
+            if (r == rb) st4s(p, 4, C.v[r]);
+    }
+
+    // GEQRT with ib = 16.  Wave 0 factors the panels one after another, each
+    // in its registers (ge_panel16); before factoring panel j it applies block
+    // j-1 to it (lookahead), while waves 1..3 apply block j-1 to the columns
+    // right of panel j on the matrix cores.  V and T of the last factored
+    // block alternate between two LDS buffers; one barrier per block.
+    __device__ __forceinline__ static void geqrt16(double *Akk, double *Tkk, double *Vkk, double *smem) {
+        double *Vb[2] = {smem, smem + 16 * LDV};
+        double *Tb[2] = {smem + 32 * LDV, smem + 32 * LDV + 256};
+        double *Pl = smem + 32 * LDV + 512 + 256;
+        const int w = __builtin_amdgcn_readfirstlane(wave_id());
+        if (w == 0) geqrt16_panel(Akk, Tkk, Vkk, 0, nullptr, nullptr, Vb[0], Tb[0], Pl);
+        __syncthreads();
+#pragma unroll 1
+        for (int s = 0; s + 1 < NB; ++s) {
+            double *Vs = Vb[s & 1], *Ts = Tb[s & 1];
+            if (w == 0) {
+                geqrt16_panel(Akk, Tkk, Vkk, s + 1, Vs, Ts, Vb[(s + 1) & 1], Tb[(s + 1) & 1], Pl);
+            } else {
+                for (int j = s + 1 + w; j < NB; j += NWAVES - 1) {
+                    Strip<B> C;
+                    strip_load<B>(C, Akk + (size_t)16 * j * B, B);
+                    panel_update<B, 16, true, false>(C, nullptr, Vs, LDV, Ts, 16 * s);
+                    strip_store<B>(C, Akk + (size_t)16 * j * B, B, s);
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // Wave 0 of geqrt16: panel j (pivot rows cj .. cj+15), after applying
+    // block j-1 (Vs, Ts) to it when j > 0; V_j and T_j go to Vn and Tn (LDS)
+    // and to Vkk, Tkk and the tile.
+    __device__ __forceinline__ static void geqrt16_panel(double *Akk, double *Tkk, double *Vkk, int j, const double *Vs,
+                                                         const double *Ts, double *Vn, double *Tn, double *Pl) {
+        const int l = lane_id();
+        const int cj = 16 * j;
+        double *colj = Akk + (size_t)cj * B;
+        {
+            Strip<B> C;
+            strip_load<B>(C, colj, B);
+            if (j > 0) {
+                panel_update<B, 16, true, false>(C, nullptr, Vs, LDV, Ts, cj - 16);
+                strip_store_block(C, colj, j - 1);  // the R rows of block j-1
+            }
+            strip_to_lds(C, Vn);
+        }
+        double x[RPL][16];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = cj + l + 64 * i;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) x[i][c] = r < B ? Vn[c * LDV + r] : 0.0;
+        }
+        ge_panel16<RPL>(x, Tn, Pl);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int rr = l + 64 * i, r = cj + rr;
+            if (r < B) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    colj[(size_t)c * B + r] = x[i][c];
+                    // dense unit-lower V: zero above the pivot, one on it
+                    const double vd = rr > c ? x[i][c] : (rr == c ? 1.0 : 0.0);
+                    Vn[c * LDV + r] = vd;
+                    Vkk[(size_t)(cj + c) * B + r] = vd;
+                }
+            }
+        }
+        for (int r = l; r < cj; r += 64) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                Vn[c * LDV + r] = 0.0;
+                Vkk[(size_t)(cj + c) * B + r] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Tkk[(size_t)cj * 16 + l + 64 * q] = Tn[l + 64 * q];
+    }
+
+    // TSQRT with ib = 16, organised as geqrt16: wave 0 factors [R_kk block;
+    // A_ik panel] pairs (ts_panel16) with lookahead, waves 1..3 apply each
+    // block to the columns right of the next panel.
+    __device__ __forceinline__ static void tsqrt16(double *Akk, double *Aik, double *Tik, double *smem) {
+        double *Vb[2] = {smem, smem + 16 * LDV};
+        double *Tb[2] = {smem + 32 * LDV, smem + 32 * LDV + 256};
+        double *Rd = smem + 32 * LDV + 512;
+        const int w = __builtin_amdgcn_readfirstlane(wave_id());
+        if (w == 0) tsqrt16_panel(Akk, Aik, Tik, 0, nullptr, nullptr, Vb[0], Tb[0], Rd);
+        __syncthreads();
+#pragma unroll 1
+        for (int s = 0; s + 1 < NB; ++s) {
+            double *Vs = Vb[s & 1], *Ts = Tb[s & 1];
+            if (w == 0) {
+                tsqrt16_panel(Akk, Aik, Tik, s + 1, Vs, Ts, Vb[(s + 1) & 1], Tb[(s + 1) & 1], Rd);
+            } else {
+                for (int j = s + 1 + w; j < NB; j += NWAVES - 1) {
+                    Strip<B> C;
+                    strip_load<B>(C, Aik + (size_t)16 * j * B, B);
+                    panel_update<B, 16, true, true>(C, Akk + (size_t)16 * j * B, Vs, LDV, Ts, 16 * s);
+                    strip_store<B>(C, Aik + (size_t)16 * j * B, B);
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    __device__ __forceinline__ static void tsqrt16_panel(double *Akk, double *Aik, double *Tik, int j, const double *Vs,
+                                                         const double *Ts, double *Vn, double *Tn, double *Rd) {
+        const int l = lane_id();
+        const int cj = 16 * j;
+        double *acol = Aik + (size_t)cj * B, *rcol = Akk + (size_t)cj * B;
+        {
+            Strip<B> C;
+            strip_load<B>(C, acol, B);
+            if (j > 0) panel_update<B, 16, true, true>(C, rcol, Vs, LDV, Ts, cj - 16);
+            strip_to_lds(C, Vn);
+        }
+        // the diagonal block of R (upper triangle; zeros below)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = l + 64 * q, r = idx & 15, c = idx >> 4;
+            Rd[idx] = r <= c ? rcol[(size_t)c * B + cj + r] : 0.0;
+        }
+        double x[RPL][16];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = l + 64 * i;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) x[i][c] = r < B ? Vn[c * LDV + r] : 0.0;
+        }
+        ts_panel16<RPL>(x, Rd, Tn, Rd + 256);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = l + 64 * i;
+            if (r < B) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    acol[(size_t)c * B + r] = x[i][c];
+                    Vn[c * LDV + r] = x[i][c];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = l + 64 * q, r = idx & 15, c = idx >> 4;
+            if (r <= c) rcol[(size_t)c * B + cj + r] = Rd[idx];
+            Tik[(size_t)cj * 16 + idx] = Tn[idx];
+        }
+    }
 
     struct Lds {
         double *P, *Ts, *G, *tau, *wv, *red;
@@ -348,6 +525,10 @@ struct TileKernels {
     // DGEQT2 (GEQRT): A_kk <- V_kk, R_kk; T_kk written; Vkk receives V_kk as
     // a dense unit-lower matrix for the LARFB tasks.
     __device__ __forceinline__ static void geqrt(double *Akk, double *Tkk, double *Vkk, double *smem) {
+        if constexpr (IB == 16) {
+            geqrt16(Akk, Tkk, Vkk, smem);
+            return;
+        }
         Lds L(smem);
         const int tid = threadIdx.x;
 #pragma unroll 1
@@ -391,6 +572,10 @@ struct TileKernels {
     // DTSQT2 (TSQRT): [R_kk; A_ik] <- R~_kk, V_ik; T_ik written.  Only the
     // upper triangle of the diagonal tile is read or written.
     __device__ __forceinline__ static void tsqrt(double *Akk, double *Aik, double *Tik, double *smem) {
+        if constexpr (IB == 16) {
+            tsqrt16(Akk, Aik, Tik, smem);
+            return;
+        }
         Lds L(smem);
         const int tid = threadIdx.x;
         constexpr int hp = IB + B;
@@ -501,7 +686,7 @@ struct FactorBody {
     __device__ double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
     __device__ double *tslot(int i, int k) const { return T + ((int64_t)k * p + i) * IB * B; }
     __device__ double *vdiag(int k) const { return Vd + (int64_t)k * B * B; }
-    __device__ void run(const Task &t, double *smem) const {
+    __device__ __forceinline__ void run(const Task &t, double *smem) const {
         const int cbeg = t.c * kStripCols, cend = min(B, cbeg + kStripCols);
         switch (t.kind) {
         case GEQRT: K::geqrt(tile(t.k, t.k), tslot(t.k, t.k), vdiag(t.k), smem); break;
@@ -526,7 +711,7 @@ struct ApplyBody {
     __device__ const double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
     __device__ const double *tslot(int i, int k) const { return T + ((int64_t)k * p + i) * IB * B; }
     __device__ double *btile(int i) const { return Bt + (int64_t)i * B * wb; }
-    __device__ void run(const Task &t, double *smem) const {
+    __device__ __forceinline__ void run(const Task &t, double *smem) const {
         const int cbeg = t.c * kStripCols, cend = min(wb, cbeg + kStripCols);
         if (t.i == t.k)
             K::template larfb<TRANS>(Vd + (int64_t)t.k * B * B, tslot(t.k, t.k), btile(t.k), cbeg, cend, smem);
@@ -545,7 +730,7 @@ struct TrsmBody {
     int64_t nrow;
     __device__ const double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
     __device__ double *btile(int i) const { return Bt + (int64_t)i * B * wb; }
-    __device__ void run(const Task &t, double *smem) const {
+    __device__ __forceinline__ void run(const Task &t, double *smem) const {
         if (t.kind == 1) {
             // G(i,j): B_i -= R_ij X_j on the matrix cores
             const double *R = tile(t.i, t.j);

@@ -40,10 +40,47 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // loads above this point, which would hold many fragments live at once.
 __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
+// ---------------------------------------------------------------------------
+// Cross-lane exchanges of doubles without the LDS unit.  Inside a 16-lane
+// row: DPP quad_perm [1,0,3,2] (lane ^ 1), quad_perm [2,3,0,1] (lane ^ 2),
+// row_half_mirror (lane i <-> 7 - i inside each group of 8) and row_ror:8
+// (lane ^ 8).  Across rows: the gfx950 permlane16/32 swaps, which given the
+// same register twice return the two rows (halves) of each pair, so their
+// sum is the sum over lane ^ 16 (lane ^ 32).  Every step adds a lane's value
+// and its partner's, so both lanes of a pair hold the same bits.
+// ---------------------------------------------------------------------------
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    int2 w = __builtin_bit_cast(int2, v);
+    w.x = __builtin_amdgcn_update_dpp(0, w.x, CTRL, 0xf, 0xf, false);
+    w.y = __builtin_amdgcn_update_dpp(0, w.y, CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, w);
+}
+
+__device__ __forceinline__ double sum_xor16(double v) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    const auto lo = __builtin_amdgcn_permlane16_swap(w.x, w.x, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(w.y, w.y, false, false);
+    return __builtin_bit_cast(double, int2{(int)lo[0], (int)hi[0]}) + __builtin_bit_cast(double, int2{(int)lo[1], (int)hi[1]});
+}
+
+__device__ __forceinline__ double sum_xor32(double v) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    const auto lo = __builtin_amdgcn_permlane32_swap(w.x, w.x, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(w.y, w.y, false, false);
+    return __builtin_bit_cast(double, int2{(int)lo[0], (int)hi[0]}) + __builtin_bit_cast(double, int2{(int)lo[1], (int)hi[1]});
+}
+
+// Sum over the wave, the same value in every lane.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_d<kDppXor1>(v);
+    v += dpp_d<kDppXor2>(v);
+    v += dpp_d<kDppHalfMirror>(v);
+    v += dpp_d<kDppRor8>(v);
+    v = sum_xor16(v);
+    return sum_xor32(v);
 }
 
 // Sum over the workgroup; every thread gets the result.  `red` holds NWAVES doubles.
@@ -249,6 +286,237 @@ __device__ void panel_t(const double *P, int hp, int ldp, const double *tau, dou
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// One-wave panel factorisation of an inner block of 16 columns.
+//
+// The panel sits in the registers of a single wave, one row per lane and
+// step (row lane + 64 i, i < RPL), all 16 columns per row: x[i][c].  A column
+// step then needs only wave-level reductions: the squared norm below the
+// pivot, and one batched reduction that yields, in a single pass over the
+// rows, both the products v_jj^T A(:, c) for the columns right of the pivot
+// (the rank-1 update) and v_c^T v_jj for the columns left of it (the next
+// column of the compact-WY T, Sec. 2.1).  No workgroup barrier is involved, so
+// the other waves of the workgroup keep updating trailing columns meanwhile.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_readlane(w.x, lane);
+    r.y = __builtin_amdgcn_readlane(w.y, lane);
+    return __builtin_bit_cast(double, r);
+}
+
+// out[c] = sum over the wave of v[c], c < 16, uniform in every lane, and
+// lds_out[c] = the same totals in LDS.  Reduce-scatter inside each 16-lane
+// row by halving exchanges (the lane ^ 8 pair keeps values 0..7 / 8..15 by
+// lane bit 3, the half-mirror pair by bit 2, then bits 1 and 0), after which
+// lane l holds its row's partial of value l & 15; the four rows are summed
+// with the two swaps and the totals read from lanes 0..15.
+__device__ __forceinline__ void wave_allsum16(const double (&v)[16], double (&out)[16], double *lds_out) {
+    const int l = lane_id();
+    double a[8], b[4], c[2];
+    bool hi = (l & 8) != 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = (hi ? v[8 + i] : v[i]) + dpp_d<kDppRor8>(hi ? v[i] : v[8 + i]);
+    hi = (l & 4) != 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] = (hi ? a[4 + i] : a[i]) + dpp_d<kDppHalfMirror>(hi ? a[i] : a[4 + i]);
+    hi = (l & 2) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) c[i] = (hi ? b[2 + i] : b[i]) + dpp_d<kDppXor2>(hi ? b[i] : b[2 + i]);
+    hi = (l & 1) != 0;
+    double d = (hi ? c[1] : c[0]) + dpp_d<kDppXor1>(hi ? c[0] : c[1]);
+    d = sum_xor32(sum_xor16(d));
+    if (l < 16) lds_out[l] = d;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) out[i] = readlane_d(d, i);
+}
+
+// Householder reflector of the column with pivot alpha and squared norm
+// sigma2 below the pivot (the unblocked algorithm of Sec. 2.1, LAPACK
+// convention): sigma2 == 0 gives tau = 0 (H = I); else
+// beta = -sgn(alpha) sqrt(alpha^2 + sigma2), tau = (beta - alpha) / beta and
+// the entries below the pivot are scaled by 1 / (alpha - beta).
+struct Reflector {
+    double tau, beta, scale;
+};
+__device__ __forceinline__ Reflector make_reflector(double alpha, double sigma2) {
+    Reflector h{0.0, alpha, 1.0};
+    if (sigma2 != 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma2);
+        h.beta = alpha >= 0.0 ? -nrm : nrm;
+        h.tau = (h.beta - alpha) / h.beta;
+        h.scale = 1.0 / (alpha - h.beta);
+    }
+    return h;
+}
+
+// Both panel kernels keep the pivot column in x[.][0]: after each step the
+// columns rotate left by one, so the step is the same code for every column
+// (no unrolling over columns, which keeps the code small).  At step jj
+// columns 1 .. 15-jj are the ones right of the pivot and columns 16-jj .. 15
+// hold v_0 .. v_jj-1; after 16 steps the columns are back in order.
+template <int RPL>
+__device__ __forceinline__ void rotate_left(double (&x)[RPL][16]) {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const double t = x[i][0];
+#pragma unroll
+        for (int c = 0; c < 15; ++c) x[i][c] = x[i][c + 1];
+        x[i][15] = t;
+    }
+}
+
+// LDS scratch of a one-wave panel: the per-lane partial products (64 rows of
+// kPartStride doubles: the padding spreads both the row writes and the
+// column reads over all banks), the Gram columns G (16 x 16, step jj writes
+// column jj in rotated order) and the taus.
+constexpr int kPartStride = 18;
+constexpr int kPanelScratch = 64 * kPartStride + 256 + 16;
+
+// Batched products of a step, P[c] = sum over the wave of v . x[.][c], the
+// same in every lane; the 16 totals also go to Gcol (LDS).  Each lane writes
+// its 16 partial sums as one row of the scratch; lane l then adds column
+// l & 15 over the 16 rows of its quarter, the two swaps add the quarters,
+// lanes 0..15 write the totals, and every lane reads them back.
+template <int RPL>
+__device__ __forceinline__ void panel_products(const double (&x)[RPL][16], const double (&v)[RPL], double (&P)[16],
+                                               double *part, double *Gcol) {
+    const int l = lane_id();
+    double pv[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) acc += v[i] * x[i][c];
+        pv[c] = acc;
+    }
+    double2 *row = reinterpret_cast<double2 *>(part + l * kPartStride);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) row[i] = double2{pv[2 * i], pv[2 * i + 1]};
+    const double *col = part + (l >> 4) * 16 * kPartStride + (l & 15);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += col[k * kPartStride];
+    s = sum_xor32(sum_xor16(s));
+    if (l < 16) Gcol[l] = s;
+    const double2 *g = reinterpret_cast<const double2 *>(Gcol);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const double2 t = g[i];
+        P[2 * i] = t.x;
+        P[2 * i + 1] = t.y;
+    }
+}
+
+// T of the block from the Gram columns and taus (compact WY, forward and
+// column-wise, Sec. 2.1): T[j][j] = tau_j,
+// T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j], where the step-j column is stored
+// rotated: G(d, j) = Gs[16 j + 16 - j + d].  Column j is computed from the
+// columns before it in LDS, lane l < 16 computing row l (T's zeros left of
+// the diagonal make the sum over d < j exact).  A runtime loop over j keeps
+// only one column's lane masks live.
+__device__ __forceinline__ void panel_t_from_gram(const double *Gs, const double *taus, double *Tl) {
+    const int l = lane_id(), r = l & 15;
+#pragma unroll 1
+    for (int j = 0; j < 16; ++j) {
+        const double tau = taus[j];
+        const double *g = Gs + 16 * j + 16 - j;
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 15; ++d)
+            if (d < j) acc += Tl[r + 16 * d] * g[d];
+        if (l < 16) Tl[l + 16 * j] = l < j ? -tau * acc : (l == j ? tau : 0.0);
+    }
+}
+
+// DTSQT2 on one inner block: x holds the b rows of A_ik (rows >= b zero) and
+// Rd (LDS, 16 x 16 column-major) the upper-triangular diagonal block of R_kk.
+// Reflector jj is [e_jj; v_jj] (Sec. 3.1): it touches row jj of Rd and all of
+// x.  On exit x holds V (the A_ik part of the reflectors), Rd the new
+// triangle, Tl the block's T.  scr: kPanelScratch doubles of LDS.
+template <int RPL>
+__device__ __forceinline__ void ts_panel16(double (&x)[RPL][16], double *Rd, double *Tl, double *scr) {
+    const int l = lane_id();
+    double *part = scr, *Gs = scr + 64 * kPartStride, *taus = Gs + 256;
+#pragma unroll 1
+    for (int jj = 0; jj < 16; ++jj) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) s += x[i][0] * x[i][0];
+        const double sigma2 = wave_sum(s);
+        const Reflector h = make_reflector(Rd[jj + 16 * jj], sigma2);
+        double v[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) v[i] = x[i][0] * h.scale;
+        double P[16];
+        double *Gcol = Gs + 16 * jj;
+        panel_products<RPL>(x, v, P, part, Gcol);
+        // w_c = R[jj][jj+c] + v^T A(:, jj+c);  R[jj][jj+c] -= tau w_c;
+        // A(:, jj+c) -= tau w_c v, for c = 1 .. 15-jj
+        const int nright = 15 - jj;
+        double tw[16];
+#pragma unroll
+        for (int c = 1; c < 16; ++c) tw[c] = c <= nright ? h.tau * (Rd[jj + 16 * (jj + c)] + P[c]) : 0.0;
+#pragma unroll
+        for (int c = 1; c < 16; ++c)
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) x[i][c] -= tw[c] * v[i];
+        if (l >= 1 && l <= nright) Rd[jj + 16 * (jj + l)] -= h.tau * (Rd[jj + 16 * (jj + l)] + Gcol[l]);
+        if (l == 0) {
+            Rd[jj + 16 * jj] = h.beta;
+            taus[jj] = h.tau;
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) x[i][0] = v[i];
+        rotate_left<RPL>(x);
+    }
+    panel_t_from_gram(Gs, taus, Tl);
+}
+
+// DGEQT2 on one inner block whose pivots are rows c0 .. c0+15 of the tile:
+// x holds rows c0 + lane + 64 i (rows >= b zero).  Pivot jj is in lane jj,
+// i = 0.  On exit the rows at and below each pivot hold beta and v, the rows
+// above the pivots are R entries, and Tl holds T.  scr as ts_panel16.
+template <int RPL>
+__device__ __forceinline__ void ge_panel16(double (&x)[RPL][16], double *Tl, double *scr) {
+    const int l = lane_id();
+    double *part = scr, *Gs = scr + 64 * kPartStride, *taus = Gs + 256;
+#pragma unroll 1
+    for (int jj = 0; jj < 16; ++jj) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+            if (l + 64 * i > jj) s += x[i][0] * x[i][0];
+        const double sigma2 = wave_sum(s);
+        const Reflector h = make_reflector(readlane_d(x[0][0], jj), sigma2);
+        // v with its unit pivot and zeros above
+        double v[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = l + 64 * i;
+            v[i] = r > jj ? x[i][0] * h.scale : (r == jj ? 1.0 : 0.0);
+        }
+        double P[16];
+        panel_products<RPL>(x, v, P, part, Gs + 16 * jj);
+        const int nright = 15 - jj;
+#pragma unroll
+        for (int c = 1; c < 16; ++c) {
+            const double tw = c <= nright ? h.tau * P[c] : 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) x[i][c] -= tw * v[i];
+        }
+        if (l == 0) taus[jj] = h.tau;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = l + 64 * i;
+            x[i][0] = r > jj ? v[i] : (r == jj ? h.beta : x[i][0]);
+        }
+        rotate_left<RPL>(x);
+    }
+    panel_t_from_gram(Gs, taus, Tl);
 }
 
 }  // namespace tqr
