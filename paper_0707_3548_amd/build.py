@@ -21,6 +21,10 @@ FLAGS = [
     "-shared",
     # no packed FP32 instructions in any generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP64 matrix-core products with their accumulators in AGPRs issue at half
+    # the rate of the VGPR form on gfx950 (35 vs 78 TFLOP/s measured): keep
+    # every MFMA destination and accumulator in VGPRs
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"),
     "-I", CSRC,
 ]

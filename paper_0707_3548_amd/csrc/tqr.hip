@@ -335,7 +335,15 @@ struct TileKernels {
     // ib = 16 panels: two V buffers (16 x LDV), two T buffers (16 x 16), the
     // 16 x 16 diagonal block of R for TSQRT, the one-wave panel scratch
     static constexpr size_t LDS_IB16 = (2 * 16 * (size_t)LDV + 2 * 256 + 256 + kPanelScratch) * sizeof(double);
-    static constexpr size_t LDS_BYTES = IB == 16 && LDS_IB16 > LDS_GENERIC ? LDS_IB16 : LDS_GENERIC;
+    // LARFB/SSRFB with ib = 16 stage V and T of the next inner block while
+    // the current one is applied: two buffers of (LDV x 16 + 16 x 16)
+    static constexpr size_t STAGE_DOUBLES = (size_t)LDV * IB + IB * IB;
+    static constexpr bool DBUF = IB == 16;
+    static constexpr size_t LDS_DBUF = DBUF ? 2 * STAGE_DOUBLES * sizeof(double) : 0;
+    static constexpr size_t LDS_MAX1 = IB == 16 && LDS_IB16 > LDS_GENERIC ? LDS_IB16 : LDS_GENERIC;
+    static constexpr size_t LDS_BYTES = LDS_DBUF > LDS_MAX1 ? LDS_DBUF : LDS_MAX1;
+    static constexpr int STAGE_V = B * IB / NT;               // V doubles per thread per block
+    static constexpr int STAGE_T = (IB * IB + NT - 1) / NT;   // T doubles per thread per block
     static constexpr int RPL = B >= 64 ? B / 64 : 1;        // panel rows per lane (one-wave panels)
 
     // A strip (matrix-core accumulator layout) into LDS as Vl[c * LDV + r].
@@ -625,6 +633,66 @@ struct TileKernels {
         for (int idx = tid; idx < IB * IB; idx += NT) Tl[idx] = T[(size_t)c0 * IB + idx];
     }
 
+    // Register half of the double-buffered staging: this thread's share of
+    // block c0 of V (B x IB) and of its T (IB x IB).
+    struct StageRegs {
+        double v[STAGE_V], t[STAGE_T];
+    };
+    __device__ __forceinline__ static void stage_fetch(const double *V, const double *T, int c0, StageRegs &R) {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < STAGE_V; ++k) {
+            const int idx = tid + k * NT, r = idx % B, c = idx / B;
+            R.v[k] = V[(size_t)(c0 + c) * B + r];
+        }
+#pragma unroll
+        for (int k = 0; k < STAGE_T; ++k) {
+            const int idx = tid + k * NT;
+            R.t[k] = idx < IB * IB ? T[(size_t)c0 * IB + idx] : 0.0;
+        }
+    }
+    __device__ __forceinline__ static void stage_commit(const StageRegs &R, double *buf) {
+        const int tid = threadIdx.x;
+        double *Vl = buf, *Tl = buf + (size_t)LDV * IB;
+#pragma unroll
+        for (int k = 0; k < STAGE_V; ++k) {
+            const int idx = tid + k * NT, r = idx % B, c = idx / B;
+            Vl[c * LDV + r] = R.v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < STAGE_T; ++k) {
+            const int idx = tid + k * NT;
+            if (idx < IB * IB) Tl[idx] = R.t[k];
+        }
+    }
+
+    // LARFB / SSRFB with double-buffered staging: block si+1 is fetched into
+    // registers before block si is applied and written to the other buffer
+    // after, so its load latency overlaps the matrix-core work; one barrier
+    // per block.  For SSRFB the wave's top rows of the block are loaded first,
+    // so that waiting for them does not wait for the prefetch.
+    template <bool TRANS, bool TS>
+    __device__ __forceinline__ static void apply_dbuf(Strip<B> &C, double *Top, const double *V, const double *T,
+                                                      int col0, bool owner, double *smem) {
+        double *buf[2] = {smem, smem + STAGE_DOUBLES};
+        StageRegs R;
+        stage_fetch(V, T, (TRANS ? 0 : NB - 1) * IB, R);
+        stage_commit(R, buf[0]);
+        __syncthreads();
+#pragma unroll 1
+        for (int si = 0; si < NB; ++si) {
+            const int c0 = (TRANS ? si : NB - 1 - si) * IB;
+            double *cur = buf[si & 1];
+            d4 Wt[IB / 16];
+            if (TS) load_top<B, IB>(Wt, Top + (size_t)col0 * B, c0);
+            if (si + 1 < NB) stage_fetch(V, T, (TRANS ? si + 1 : NB - 2 - si) * IB, R);
+            panel_update<B, IB, TRANS, TS>(C, TS ? Top + (size_t)col0 * B : nullptr, cur, LDV, cur + (size_t)LDV * IB,
+                                           c0, owner, TS ? Wt : nullptr);
+            if (si + 1 < NB) stage_commit(R, buf[(si + 1) & 1]);
+            __syncthreads();
+        }
+    }
+
     // DLARFB (LARFB) on columns [cbeg, cend) of a b-row tile with the
     // reflectors of a diagonal tile (Vd: V_kk as a dense unit-lower matrix,
     // T_kk): C <- Q_kk^T C (trans) or Q_kk C.
@@ -639,13 +707,17 @@ struct TileKernels {
         const bool owner = want < cend;
         Strip<B> C;
         strip_load<B>(C, Cb + (size_t)col0 * B, B);
+        if constexpr (DBUF) {
+            apply_dbuf<TRANS, false>(C, nullptr, Vd, Tkk, col0, owner, smem);
+        } else {
 #pragma unroll 1
-        for (int si = 0; si < NB; ++si) {
-            const int c0 = (TRANS ? si : NB - 1 - si) * IB;
-            __syncthreads();
-            stage(Vd, Tkk, c0, Vl, Tl);
-            __syncthreads();
-            panel_update<B, IB, TRANS, false>(C, nullptr, Vl, LDV, Tl, c0);
+            for (int si = 0; si < NB; ++si) {
+                const int c0 = (TRANS ? si : NB - 1 - si) * IB;
+                __syncthreads();
+                stage(Vd, Tkk, c0, Vl, Tl);
+                __syncthreads();
+                panel_update<B, IB, TRANS, false>(C, nullptr, Vl, LDV, Tl, c0);
+            }
         }
         if (owner) strip_store<B>(C, Cb + (size_t)col0 * B, B);
     }
@@ -661,13 +733,17 @@ struct TileKernels {
         const bool owner = want < cend;
         Strip<B> C;
         strip_load<B>(C, Cb + (size_t)col0 * B, B);
+        if constexpr (DBUF) {
+            apply_dbuf<TRANS, true>(C, Top, Vik, Tik, col0, owner, smem);
+        } else {
 #pragma unroll 1
-        for (int si = 0; si < NB; ++si) {
-            const int c0 = (TRANS ? si : NB - 1 - si) * IB;
-            __syncthreads();
-            stage(Vik, Tik, c0, Vl, Tl);
-            __syncthreads();
-            panel_update<B, IB, TRANS, true>(C, Top + (size_t)col0 * B, Vl, LDV, Tl, c0, owner);
+            for (int si = 0; si < NB; ++si) {
+                const int c0 = (TRANS ? si : NB - 1 - si) * IB;
+                __syncthreads();
+                stage(Vik, Tik, c0, Vl, Tl);
+                __syncthreads();
+                panel_update<B, IB, TRANS, true>(C, Top + (size_t)col0 * B, Vl, LDV, Tl, c0, owner);
+            }
         }
         if (owner) strip_store<B>(C, Cb + (size_t)col0 * B, B);
     }

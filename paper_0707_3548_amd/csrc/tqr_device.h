@@ -37,7 +37,8 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 }
 
 // Keeps the instruction scheduler from hoisting the next row block's operand
-// loads above this point, which would hold many fragments live at once.
+// loads above this point, which would hold many fragments live at once (used
+// for inner blocks wider than 16; with 16 the early loads hide LDS latency).
 __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
 // ---------------------------------------------------------------------------
@@ -135,16 +136,33 @@ __device__ __forceinline__ void strip_store(const Strip<B> &s, double *col0, int
 //   W = V^T C,  W = op(T) W,  C -= V W, over rows c0..B-1 only.
 // op(T) = T^T applies Q^T (factorisation); T applies Q.  A wave that only
 // duplicates another wave's columns passes write_top = false.
+// The IB top rows of the wave's 16 columns in the upper tile (the TS form's
+// W initial value), in the accumulator layout.
+template <int B, int IB>
+__device__ __forceinline__ void load_top(d4 (&W)[IB / 16], const double *top, int c0) {
+    const int l = lane_id();
+    const double *tp = top + (size_t)(l & 15) * B + c0 + (l >> 4);
+#pragma unroll
+    for (int a = 0; a < IB / 16; ++a) W[a] = ld4s(tp + 16 * a, 4);
+}
+
+// With `Wtop` the TS form takes the top rows already loaded by load_top
+// (so that their load can be issued ahead of other memory traffic).
 template <int B, int IB, bool TRANS, bool TS>
 __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const double *Vl, int ldv, const double *Tl,
-                                             int c0, bool write_top = true) {
+                                             int c0, bool write_top = true, const d4 *Wtop = nullptr) {
     constexpr int NA = IB / 16;
     const int l = lane_id();
     const int rb0 = TS ? 0 : c0 / 16;
-    d4 W[NA], W2[NA];
+    d4 W[NA], W2[NA], Wt[NA];
     double *tp = TS ? top + (size_t)(l & 15) * B + c0 + (l >> 4) : nullptr;
+    // the top rows are added after V^T C, so that their load latency is
+    // hidden behind the matrix-core products
 #pragma unroll
-    for (int a = 0; a < NA; ++a) W[a] = TS ? ld4s(tp + 16 * a, 4) : d4{0.0, 0.0, 0.0, 0.0};
+    for (int a = 0; a < NA; ++a) {
+        if (TS) Wt[a] = Wtop ? Wtop[a] : ld4s(tp + 16 * a, 4);
+        W[a] = d4{0.0, 0.0, 0.0, 0.0};
+    }
     // k-slice (rb, r): rows 16rb + 4r + {0..3}; A operand V^T[16a + l%16][16rb + 4r + l/16]
     const double *vp = Vl + (l & 15) * ldv + (l >> 4);
 #pragma unroll
@@ -158,7 +176,11 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
             W[a] = mfma(q[8], C.v[rb].z, W[a]);
             W[a] = mfma(q[12], C.v[rb].w, W[a]);
         }
-        sched_fence();
+        if constexpr (NA > 1) sched_fence();
+    }
+    if (TS) {
+#pragma unroll
+        for (int a = 0; a < NA; ++a) W[a] += Wt[a];
     }
     // W2 = op(T) W; A operand of k-slice (a, r): op(T)[16o + l%16][16a + 4r + l/16]
 #pragma unroll
@@ -179,7 +201,7 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
     }
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
-        if (TS && write_top) st4s(tp + 16 * a, 4, ld4s(tp + 16 * a, 4) - W2[a]);
+        if (TS && write_top) st4s(tp + 16 * a, 4, Wt[a] - W2[a]);
         W2[a] = -W2[a];
     }
     // C -= V W2; A operand of k-slice (a, r): V[16rb + l%16][16a + 4r + l/16]
@@ -195,7 +217,7 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
             C.v[rb] = mfma(q[8 * ldv], W2[a].z, C.v[rb]);
             C.v[rb] = mfma(q[12 * ldv], W2[a].w, C.v[rb]);
         }
-        sched_fence();
+        if constexpr (NA > 1) sched_fence();
     }
 }
 
