@@ -2,10 +2,12 @@
 
 A step is one tiled QR factorisation (tqr_factor: column-major -> tiles, the
 persistent task-graph launch, tiles -> column-major) of an 8192 x 8192 N(0,1)
-matrix with tile_b = 256, inner_ib = 32; every timed step factors its own
+matrix with tile_b = 256, inner_ib = 16; every timed step factors its own
 pristine copy of the input, resident in HBM before the timed region starts.
-The tall-skinny 65536 x 1024 U[-1,1] factorisation (same tiling) is reported
-beside it.  Prints one JSON line.
+`value` is the rate on the standard Householder count 2n^2(m - n/3); the
+tiled method's executed count and the (4mn^2 - 4n^3/3) convention are
+reported beside it.  The tall-skinny 65536 x 1024 U[-1,1] factorisation
+(same tiling) is reported beside it too.  Prints one JSON line.
 """
 import argparse
 import ctypes
@@ -21,7 +23,8 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_factor_8192_b256.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_0707_3548_amd", "csrc", f) for f in ("tqr.hip", "tqr_device.h", "tqr_graph.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0707_3548_amd", "csrc", f) for f in ("tqr.hip", "tqr_device.h", "tqr_graph.h")] + \
+    [os.path.join(ROOT, "paper_0707_3548_amd", "build.py")]
 
 
 def kernel_source_hash() -> str:
@@ -35,13 +38,13 @@ def kernel_source_hash() -> str:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--tile-b", type=int, default=256)
-    ap.add_argument("--inner-ib", type=int, default=32)
+    ap.add_argument("--inner-ib", type=int, default=16)
     ap.add_argument("--policy", choices=["paper", "lookahead"], default="paper")
-    ap.add_argument("--cpu-cols", type=int, default=1024, help="columns of the oracle's CPU sample")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle's CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tall", action="store_true")
     return ap.parse_args()
@@ -49,8 +52,8 @@ def parse():
 
 def time_factor(tqr, torch, A_host, b, ib, steps, warmup, policy):
     """Factor `warmup + steps` device copies of A; returns (wall ms/step over
-    the timed steps, kernel ms/step from HIP events around the scheduler
-    launch, the last factored matrix)."""
+    the timed steps, the per-step scheduler-launch times from HIP events, the
+    last factored matrix, its workspace)."""
     m, n = A_host.shape
     src = tqr.fortran(torch.from_numpy(A_host).cuda())
     copies = [src.clone() for _ in range(warmup + steps)]  # clone keeps the column-major strides
@@ -68,7 +71,7 @@ def time_factor(tqr, torch, A_host, b, ib, steps, warmup, policy):
         tqr.factor(copies[warmup + s], b, ib, ws, policy=pol, status=status, events=evs[s])
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3 / steps
-    kern_ms = sum(ev.elapsed_ms(a, e) for a, e in evs) / steps
+    kern_ms = [ev.elapsed_ms(a, e) for a, e in evs]
     if int(status.item()) != 0:
         raise RuntimeError(f"scheduler reported status {int(status.item())}")
     for a, e in evs:
@@ -101,22 +104,34 @@ def spot_check(torch, A_host, F, n_check=256):
     return {"column_norm_rel_err": col_err, "leading_block_rel_err": lead_err}
 
 
-def cpu_baseline(A_host, cols):
+def cpu_baseline(A_host, seconds):
     """The oracle (plain FP64 Householder QR, C, OpenMP over the trailing
-    columns) on the leading `cols` columns of the same matrix."""
+    columns) on the leading columns of the same matrix: a 512-column run sets
+    the rate, then the widest power-of-two column count whose predicted time
+    stays within `seconds` is timed."""
     import numpy as np
     import oracle
 
-    sample = np.asfortranarray(A_host[:, :cols])
+    m = A_host.shape[0]
     threads = oracle.num_threads(omp=True)
-    t0 = time.perf_counter()
-    oracle.geqr2(sample, omp=True)
-    dt = time.perf_counter() - t0
-    m, n = sample.shape
-    flops = 2.0 * n * n * (m - n / 3.0)
-    return {"value": flops / dt / 1e9, "unit": "Gflop/s", "cores": threads, "kind": "oracle",
-            "sample": f"unblocked Householder QR of the leading {m}x{n} columns of the same 8192x8192 input "
-                      f"(standard count 2n^2(m-n/3)); {dt:.1f} s"}
+
+    def run(cols):
+        sample = np.asfortranarray(A_host[:, :cols])
+        t0 = time.perf_counter()
+        oracle.geqr2(sample, omp=True)
+        return time.perf_counter() - t0
+
+    def std(cols):
+        return 2.0 * cols * cols * (m - cols / 3.0)
+
+    rate = std(512) / run(512)
+    cols = 512
+    while cols * 2 <= A_host.shape[1] and std(cols * 2) / rate <= seconds:
+        cols *= 2
+    dt = run(cols)
+    return {"value": round(std(cols) / dt / 1e9, 3), "unit": "Gflop/s", "cores": threads, "kind": "oracle",
+            "sample": f"unblocked Householder QR (OpenMP over the trailing columns) of the leading {m}x{cols} "
+                      f"columns of the same 8192x8192 input, standard count 2n^2(m-n/3); {dt:.1f} s"}
 
 
 def traffic_from_profile(per_launch_flops):
@@ -152,7 +167,8 @@ def main():
     print(f"bench: generating {n}x{n} N(0,1)", file=sys.stderr, flush=True)
     A = workloads.gaussian(n, n, seed=0)
     print("bench: timing the 8192^2 factorisation", file=sys.stderr, flush=True)
-    wall_ms, kern_ms, F, ws = time_factor(tqr, torch, A, b, ib, args.steps, args.warmup, args.policy)
+    wall_ms, kern_list, F, ws = time_factor(tqr, torch, A, b, ib, args.steps, args.warmup, args.policy)
+    kern_ms = sum(kern_list) / len(kern_list)
     std = flops.standard(n, n)
     exe = flops.tiled(n, n, b, ib)
     value = std / (wall_ms * 1e-3) / 1e9
@@ -166,17 +182,19 @@ def main():
     if not args.no_tall:
         print("bench: tall-skinny 65536x1024", file=sys.stderr, flush=True)
         At = workloads.uniform(65536, 1024, seed=1)
-        t_wall, t_kern, Ft, wst = time_factor(tqr, torch, At, b, ib, max(2, args.steps // 2), 1, args.policy)
-        tall = {"workload": "tiled QR 65536x1024 U[-1,1], tile_b=256, inner_ib=32",
+        t_wall, t_kl, Ft, wst = time_factor(tqr, torch, At, b, ib, max(2, args.steps // 4), 1, args.policy)
+        t_kern = sum(t_kl) / len(t_kl)
+        tall = {"workload": f"tiled QR 65536x1024 U[-1,1], tile_b={b}, inner_ib={ib}",
                 "ms_per_step": round(t_wall, 3), "gflops_standard": round(flops.standard(65536, 1024) / t_wall / 1e6, 1),
                 "gflops_tiled_executed": round(flops.tiled(65536, 1024, b, ib) / t_kern / 1e6, 1)}
+        print(f"bench: tall-skinny {t_wall:.1f} ms/step", file=sys.stderr, flush=True)
         del Ft, wst
         torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu:
-        print(f"bench: oracle on the host ({args.cpu_cols} columns)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(A, args.cpu_cols)
+        print(f"bench: oracle on the host (about {args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(A, args.cpu_seconds)
 
     traffic = traffic_from_profile(exe)
     line = {
@@ -198,7 +216,9 @@ def main():
         "rates": {"gflops_standard_2n2(m-n/3)": round(value, 2),
                   "gflops_tiled_executed": round(exe / (wall_ms * 1e-3) / 1e9, 2),
                   "gflops_4mn2-4n3/3": round(flops.bj_formula(n, n) / (wall_ms * 1e-3) / 1e9, 2),
-                  "scheduler_kernel_ms": round(kern_ms, 3)},
+                  "scheduler_kernel_ms": round(kern_ms, 3),
+                  "scheduler_kernel_ms_median": round(sorted(kern_list)[len(kern_list) // 2], 3),
+                  "scheduler_kernel_ms_min": round(min(kern_list), 3)},
         "roofline": {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved_tf / FP64_MFMA_PEAK_TFLOPS, 4),
                      "traffic": traffic},
