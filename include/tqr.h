@@ -133,6 +133,18 @@ tqr_status tqr_apply_q(int64_t m, int64_t n, int64_t nrhs, const double *A, int6
                        const double *T, int tile_b, int inner_ib, double *B, int64_t ldb,
                        void *work, int64_t work_bytes, hipStream_t stream);
 
+/* The thin Q of the factorisation, formed explicitly: Q[0:m, 0:n] <- Q [I_n; 0]
+ * (what LAPACK's DORGQR returns; Sec. 5 lists the Q-forming and Q-applying
+ * routines as the natural companions of the tiled factorisation).  Q is
+ * filled with [I_n; 0] and the transformations of tqr_apply_q are applied.
+ *   A, T : the output of tqr_factor with the same m, n, tile_b, inner_ib.
+ *   Q    : device, m x n column-major, leading dimension ldq; written.
+ *   work : at least tqr_workspace_bytes(m, n, n, tile_b, inner_ib) bytes.
+ * Errors: -1 m, -2 n (also n > 65535), -3 A null, -4 lda, -5 T null,
+ * -6 tile_b, -7 inner_ib, -8 Q null, -9 ldq, -10 work null, -11 work_bytes. */
+tqr_status tqr_form_q(int64_t m, int64_t n, const double *A, int64_t lda, const double *T, int tile_b,
+                      int inner_ib, double *Q, int64_t ldq, void *work, int64_t work_bytes, hipStream_t stream);
+
 /* Least squares min ||A X - B||_F for m >= n (the problem of Sec. 2.1 solved
  * with the tiled factorisation, as LAPACK's dgels does with dgeqrf):
  * factor A (overwritten as by tqr_factor, T written), B <- Q^T B, then

@@ -1018,6 +1018,13 @@ __global__ void k_unit_lower(const double *__restrict__ W, int p, int b, double 
     }
 }
 
+// Q[0:m, 0:n] = [I_n; 0] (column-major, leading dimension ldq); grid
+// (ceil(m / 256), n).
+__global__ void k_eye(double *Q, int64_t ldq, int64_t m) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+    if (r < m) Q[c * ldq + r] = r == c ? 1.0 : 0.0;
+}
+
 // d_info: smallest 1-based index k with R(k,k) == 0, else 0.
 __global__ void k_diag_info(const double *W, int p, int b, int64_t n, int32_t *info) {
     __shared__ int32_t best;
@@ -1367,6 +1374,27 @@ tqr_status tqr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A, int
 tqr_status tqr_apply_q(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *T, int tile_b,
                        int inner_ib, double *B, int64_t ldb, void *work, int64_t work_bytes, hipStream_t stream) {
     return apply_common(false, m, n, nrhs, A, lda, T, tile_b, inner_ib, B, ldb, work, work_bytes, stream);
+}
+
+tqr_status tqr_form_q(int64_t m, int64_t n, const double *A, int64_t lda, const double *T, int tile_b, int inner_ib,
+                      double *Q, int64_t ldq, void *work, int64_t work_bytes, hipStream_t stream) {
+    if (m < 0 || m < n) return set_err(-1, "m must be >= max(n, 0)");
+    if (n < 0) return set_err(-2, "n must be >= 0");
+    if (m == 0 || n == 0) return TQR_OK;
+    if (!A) return set_err(-3, "A is null");
+    if (lda < std::max<int64_t>(1, m)) return set_err(-4, "lda < max(1, m)");
+    if (!T) return set_err(-5, "T is null");
+    if (!(tile_b == 16 || tile_b == 32 || tile_b == 64 || tile_b == 128 || tile_b == 256))
+        return set_err(-6, "tile_b must be one of 16, 32, 64, 128, 256");
+    if (!tiles_ok(tile_b, inner_ib)) return set_err(-7, "unsupported inner_ib");
+    if (!Q) return set_err(-8, "Q is null");
+    if (ldq < std::max<int64_t>(1, m)) return set_err(-9, "ldq < max(1, m)");
+    if (!work) return set_err(-10, "work is null");
+    if (work_bytes < tqr_workspace_bytes(m, n, n, tile_b, inner_ib)) return set_err(-11, "work_bytes too small");
+    if (n > 65535) return set_err(-2, "n > 65535 columns");
+    hipLaunchKernelGGL(k_eye, dim3((unsigned)cdiv(m, 256), (unsigned)n), dim3(256), 0, stream, Q, ldq, m);
+    HIPCHK(hipGetLastError());
+    return apply_common(false, m, n, n, A, lda, T, tile_b, inner_ib, Q, ldq, work, work_bytes, stream);
 }
 
 tqr_status tqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb, int tile_b,

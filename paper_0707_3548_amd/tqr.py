@@ -66,6 +66,8 @@ def lib() -> ctypes.CDLL:
         for f in ("tqr_apply_qt", "tqr_apply_q"):
             getattr(L, f).argtypes = [i64, i64, i64, dp, i64, dp, i32, i32, dp, i64, vp, i64, vp]
             getattr(L, f).restype = i32
+        L.tqr_form_q.argtypes = [i64, i64, dp, i64, dp, i32, i32, dp, i64, vp, i64, vp]
+        L.tqr_form_q.restype = i32
         L.tqr_solve_ls.argtypes = [i64, i64, i64, dp, i64, dp, i64, i32, i32, dp, vp, i64, vp, vp]
         L.tqr_solve_ls.restype = i32
         L.tqr_last_error_string.argtypes = []
@@ -166,6 +168,20 @@ def apply_qt(A, T, B, tile_b, inner_ib, ws=None):
 def apply_q(A, T, B, tile_b, inner_ib, ws=None):
     """B <- Q B in place."""
     return _apply("tqr_apply_q", A, T, B, tile_b, inner_ib, ws)
+
+
+def form_q(A, T, tile_b, inner_ib, Q: torch.Tensor | None = None, ws: Workspace | None = None):
+    """The explicit thin Q (m x n, column-major) of a factorisation from
+    ``factor``; written into ``Q`` if given, else into a new tensor."""
+    m, n = A.shape
+    if Q is None:
+        Q = torch.empty((n, m), dtype=torch.float64, device=A.device).t()
+    if ws is None:
+        ws = Workspace(m, n, n, tile_b, inner_ib, A.device)
+    rc = lib().tqr_form_q(m, n, A.data_ptr(), _ld(A), T.data_ptr(), tile_b, inner_ib, Q.data_ptr(), _ld(Q),
+                          ws.work.data_ptr(), ws.work.numel(), _stream())
+    _check("tqr_form_q", rc)
+    return Q
 
 
 def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None):

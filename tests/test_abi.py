@@ -75,3 +75,19 @@ def test_apply_and_solve_argument_checks(lib):
     assert lib.tqr_apply_q(8, 8, 1, fake, 8, None, 64, 16, fake, 8, fake, big, None) == -6
     assert lib.tqr_solve_ls(8, 8, 1, fake, 8, fake, 8, 64, 16, fake, fake, big, None, None) == -13
     assert lib.tqr_solve_ls(8, 9, 1, fake, 8, fake, 8, 64, 16, fake, fake, big, fake, None) == -1
+
+
+def test_form_q_argument_checks(lib):
+    fake = ctypes.c_void_p(256)
+    big = 1 << 40
+    assert lib.tqr_form_q(8, 9, fake, 8, fake, 64, 16, fake, 8, fake, big, None) == -1
+    assert lib.tqr_form_q(8, 8, None, 8, fake, 64, 16, fake, 8, fake, big, None) == -3
+    assert lib.tqr_form_q(8, 8, fake, 4, fake, 64, 16, fake, 8, fake, big, None) == -4
+    assert lib.tqr_form_q(8, 8, fake, 8, None, 64, 16, fake, 8, fake, big, None) == -5
+    assert lib.tqr_form_q(8, 8, fake, 8, fake, 48, 16, fake, 8, fake, big, None) == -6
+    assert lib.tqr_form_q(8, 8, fake, 8, fake, 64, 24, fake, 8, fake, big, None) == -7
+    assert lib.tqr_form_q(8, 8, fake, 8, fake, 64, 16, None, 8, fake, big, None) == -8
+    assert lib.tqr_form_q(8, 8, fake, 8, fake, 64, 16, fake, 7, fake, big, None) == -9
+    assert lib.tqr_form_q(8, 8, fake, 8, fake, 64, 16, fake, 8, None, big, None) == -10
+    assert lib.tqr_form_q(8, 8, fake, 8, fake, 64, 16, fake, 8, fake, 16, None) == -11
+    assert lib.tqr_form_q(0, 0, None, 1, None, 64, 16, None, 1, None, 0, None) == 0

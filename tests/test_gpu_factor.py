@@ -227,3 +227,24 @@ def test_solve_ls_reports_zero_diagonal():
     _, info = tqr.solve_ls(dA, dB, 32, 16)
     torch.cuda.synchronize()
     assert int(info.item()) == 11
+
+
+@pytest.mark.parametrize("m,n,b,ib", [(512, 512, 64, 16), (300, 200, 64, 32), (257, 129, 256, 16), (40, 17, 16, 16)])
+def test_form_q_matches_tiled_model(m, n, b, ib):
+    """tqr_form_q against the thin Q of the tiled model of Algorithm 1
+    (oracle/tiled.py), elementwise; and the bounds of the unblocked oracle:
+    ||Q^T Q - I|| and ||A - Q R|| within 10 n eps."""
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    _say(f"case form_q m={m} n={n} b={b} ib={ib}")
+    A = workloads.gaussian(m, n, seed=12)
+    dA, ws = run_factor(A, b, ib)
+    Q = tqr.form_q(dA, ws.T, b, ib)
+    torch.cuda.synchronize()
+    Qg = Q.cpu().numpy()
+    tiles, Tm = tiled.factor(A, b, ib)
+    Qm = tiled.form_q(tiles, Tm, m, n)
+    assert np.abs(Qg - Qm).max() < 1e-12 * max(1, n // 64)
+    R = np.triu(dA.cpu().numpy()[:n, :])
+    assert oracle.orth_error(Qg) <= 10 * n * EPS
+    assert oracle.fact_error(A, Qg, R) <= 10 * n * EPS
