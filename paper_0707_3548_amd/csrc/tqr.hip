@@ -485,10 +485,11 @@ struct TileKernels {
             if (j > 0) panel_update<B, 16, true, true>(C, rcol, Vs, LDV, Ts, cj - 16);
             strip_to_lds(C, Vn);
         }
-        // the diagonal block of R (upper triangle; zeros below)
+        // the diagonal block of R (upper triangle), row-major with row r
+        // rotated left by r (the layout ts_panel16 works in)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int idx = l + 64 * q, r = idx & 15, c = idx >> 4;
+            const int idx = l + 64 * q, r = idx >> 4, c = (r + (idx & 15)) & 15;
             Rd[idx] = r <= c ? rcol[(size_t)c * B + cj + r] : 0.0;
         }
         double x[RPL][16];
@@ -512,7 +513,7 @@ struct TileKernels {
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int idx = l + 64 * q, r = idx & 15, c = idx >> 4;
+            const int idx = l + 64 * q, r = idx >> 4, c = (r + (idx & 15)) & 15;
             if (r <= c) rcol[(size_t)c * B + cj + r] = Rd[idx];
             Tik[(size_t)cj * 16 + idx] = Tn[idx];
         }

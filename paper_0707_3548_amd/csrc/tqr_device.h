@@ -455,40 +455,63 @@ __device__ __forceinline__ void panel_t_from_gram(const double *Gs, const double
 }
 
 // DTSQT2 on one inner block: x holds the b rows of A_ik (rows >= b zero) and
-// Rd (LDS, 16 x 16 column-major) the upper-triangular diagonal block of R_kk.
-// Reflector jj is [e_jj; v_jj] (Sec. 3.1): it touches row jj of Rd and all of
-// x.  On exit x holds V (the A_ik part of the reflectors), Rd the new
-// triangle, Tl the block's T.  scr: kPanelScratch doubles of LDS.
+// Rr (LDS) the upper-triangular diagonal block of R_kk, row-major with each
+// row r rotated left by r (Rr[16 r + c] = R[r][(r + c) mod 16], zeros where
+// the column wraps), so that at step jj row jj lines up with the rotated
+// columns of x.  Reflector jj is [e_jj; v_jj] (Sec. 3.1): it touches row jj
+// of R and all of x.  On exit x holds V (the A_ik part of the reflectors), Rr
+// the new triangle (same layout), Tl the block's T.  scr: kPanelScratch
+// doubles of LDS.
 template <int RPL>
-__device__ __forceinline__ void ts_panel16(double (&x)[RPL][16], double *Rd, double *Tl, double *scr) {
+__device__ __forceinline__ void ts_panel16(double (&x)[RPL][16], double *Rr, double *Tl, double *scr) {
     const int l = lane_id();
     double *part = scr, *Gs = scr + 64 * kPartStride, *taus = Gs + 256;
 #pragma unroll 1
     for (int jj = 0; jj < 16; ++jj) {
+        // row jj of R, rotated: rr[0] is the pivot, rr[c] is column jj + c
+        double rr[16];
+        const double2 *rp = reinterpret_cast<const double2 *>(Rr + 16 * jj);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const double2 t = rp[i];
+            rr[2 * i] = t.x;
+            rr[2 * i + 1] = t.y;
+        }
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) s += x[i][0] * x[i][0];
         const double sigma2 = wave_sum(s);
-        const Reflector h = make_reflector(Rd[jj + 16 * jj], sigma2);
+        const Reflector h = make_reflector(rr[0], sigma2);
         double v[RPL];
 #pragma unroll
         for (int i = 0; i < RPL; ++i) v[i] = x[i][0] * h.scale;
         double P[16];
-        double *Gcol = Gs + 16 * jj;
-        panel_products<RPL>(x, v, P, part, Gcol);
+        panel_products<RPL>(x, v, P, part, Gs + 16 * jj);
         // w_c = R[jj][jj+c] + v^T A(:, jj+c);  R[jj][jj+c] -= tau w_c;
-        // A(:, jj+c) -= tau w_c v, for c = 1 .. 15-jj
+        // A(:, jj+c) -= tau w_c v, for c = 1 .. 15-jj (the columns past
+        // 15-jj hold earlier reflectors: their factor is zero, and groups of
+        // four such columns are skipped by a uniform branch)
         const int nright = 15 - jj;
         double tw[16];
 #pragma unroll
-        for (int c = 1; c < 16; ++c) tw[c] = c <= nright ? h.tau * (Rd[jj + 16 * (jj + c)] + P[c]) : 0.0;
+        for (int c = 1; c < 16; ++c) tw[c] = c <= nright ? h.tau * (rr[c] + P[c]) : 0.0;
 #pragma unroll
-        for (int c = 1; c < 16; ++c)
+        for (int g = 0; g < 4; ++g) {
+            if (g > 0 && 4 * g > nright) continue;
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) x[i][c] -= tw[c] * v[i];
-        if (l >= 1 && l <= nright) Rd[jj + 16 * (jj + l)] -= h.tau * (Rd[jj + 16 * (jj + l)] + Gcol[l]);
+            for (int c = 4 * g; c < 4 * g + 4; ++c) {
+                if (c == 0) continue;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) x[i][c] -= tw[c] * v[i];
+            }
+        }
         if (l == 0) {
-            Rd[jj + 16 * jj] = h.beta;
+            rr[0] = h.beta;
+#pragma unroll
+            for (int c = 1; c < 16; ++c) rr[c] -= tw[c];
+            double2 *wp = reinterpret_cast<double2 *>(Rr + 16 * jj);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) wp[i] = double2{rr[2 * i], rr[2 * i + 1]};
             taus[jj] = h.tau;
         }
 #pragma unroll
@@ -525,10 +548,15 @@ __device__ __forceinline__ void ge_panel16(double (&x)[RPL][16], double *Tl, dou
         panel_products<RPL>(x, v, P, part, Gs + 16 * jj);
         const int nright = 15 - jj;
 #pragma unroll
-        for (int c = 1; c < 16; ++c) {
-            const double tw = c <= nright ? h.tau * P[c] : 0.0;
+        for (int g = 0; g < 4; ++g) {
+            if (g > 0 && 4 * g > nright) continue;
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) x[i][c] -= tw * v[i];
+            for (int c = 4 * g; c < 4 * g + 4; ++c) {
+                if (c == 0) continue;
+                const double tw = c <= nright ? h.tau * P[c] : 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) x[i][c] -= tw * v[i];
+            }
         }
         if (l == 0) taus[jj] = h.tau;
 #pragma unroll
