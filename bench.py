@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle's CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tall", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=32)
     return ap.parse_args()
 
 
@@ -134,6 +136,40 @@ def cpu_baseline(A_host, seconds):
                       f"columns of the same 8192x8192 input, standard count 2n^2(m-n/3); {dt:.1f} s"}
 
 
+def serving_leg(count: int):
+    """The serving loop on the least-squares request stream (m log-uniform in
+    [256, 8192], n uniform in [m/8, m], 1-4 right-hand sides, cond
+    log-uniform in [1e1, 1e6], Poisson arrivals): once at the target rate
+    2000 req/s, which saturates one GPU (throughput and queueing latency),
+    once at 10 req/s (latency without queueing).  FP64 answers from the FP64
+    solve; host data pinned before the clock starts, copies in and out
+    timed."""
+    from paper_0707_3548_amd import serving, workloads
+
+    out = {"workload": "least-squares requests, m log-uniform [256, 8192], n uniform [m/8, m], 1-4 RHS, "
+                       "cond log-uniform [1e1, 1e6], FP64 solve (factor, Q^T B, back substitution) per request, "
+                       "8 streams, admission by HBM footprint"}
+    for name, rate, seed in (("offered_2000_per_s", 2000.0, 3), ("offered_10_per_s", 10.0, 4)):
+        arr = workloads.arrivals(rate=rate, count=count, seed=seed)
+        ex = serving.GpuExecutor(slots=8)
+        reqs = []
+        for i, r in enumerate(arr):
+            A, b, _ = workloads.ls_request(r["m"], r["n"], r["nrhs"], r["cond"], r["seed"])
+            reqs.append(ex.prepare(serving.Request(i, r["t"], r["m"], r["n"], r["nrhs"]), A, b))
+        sch = serving.Scheduler(8, 64 << 30, ex.launch, ex.poll)
+        done = sch.run(reqs)
+        st = serving.latency_stats(done)
+        span = max(c.t_done for c in done) - min(c.t_arrive for c in done)
+        st["gflop_per_s"] = sum(2.0 * r.n * r.n * (r.m - r.n / 3.0) for r in reqs) / span / 1e9
+        bad = sum(int(c.result["info"][0]) != 0 for c in done)
+        out[name] = {k: round(v, 3) for k, v in st.items()} | {"peak_in_flight": sch.peak_inflight,
+                                                             "peak_hbm_gb": round(sch.peak_bytes / 1e9, 3),
+                                                             "nonzero_info": bad}
+        print(f"bench: serving at {rate:g} req/s: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def traffic_from_profile(per_launch_flops):
     """HBM bytes per launch of the scheduler kernel, from the committed
     rocprofv3 counter summary, if it was taken on the current kernel sources."""
@@ -191,6 +227,12 @@ def main():
         del Ft, wst
         torch.cuda.empty_cache()
 
+    serving_out = None
+    if not args.no_serving:
+        print("bench: serving loop", file=sys.stderr, flush=True)
+        serving_out = serving_leg(args.serving_requests)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu:
         print(f"bench: oracle on the host (about {args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
@@ -225,6 +267,7 @@ def main():
         "cpu_baseline": cpu,
         "check": check,
         "tall_skinny": tall,
+        "serving": serving_out,
     }
     print(json.dumps(line), flush=True)
 

@@ -159,6 +159,17 @@ tqr_status tqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t l
                         int tile_b, int inner_ib, double *T, void *work, int64_t work_bytes,
                         int32_t *d_info, hipStream_t stream);
 
+/* tqr_solve_ls with execution options (a serving loop runs several solves
+ * at once and sizes each one's worker count).  The options apply to all
+ * three phases (factorisation, Q^T B, back substitution): workgroups,
+ * policy, abort flag, wait bound, and status (set by the factorisation, then
+ * overwritten only by a later phase's TQR_EABORTED); event_begin / event_end
+ * bracket the whole solve; trace is ignored; mode must be
+ * TQR_MODE_PERSISTENT.  Errors as tqr_solve_ls; -15 for bad options. */
+tqr_status tqr_solve_ls_ex(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb,
+                           int tile_b, int inner_ib, double *T, void *work, int64_t work_bytes,
+                           int32_t *d_info, hipStream_t stream, const tqr_options *options);
+
 /* Description of the last error returned to the calling host thread. */
 const char *tqr_last_error_string(void);
 

@@ -1005,7 +1005,14 @@ __global__ void __launch_bounds__(NT) k_one_task(G g, Body body, int64_t t) {
     body.run(g.decode(t), smem);
 }
 
-__global__ void k_copy_status(const SchedState *st, int32_t *out) { *out = st->status; }
+// Copies the launch's status word; with only_errors a zero status leaves
+// *out as it is (so a later phase does not hide an earlier phase's abort).
+__global__ void k_copy_status(const SchedState *st, int32_t *out, int only_errors) {
+    const int32_t v = st->status;
+    if (!only_errors || v != 0) *out = v;
+}
+
+__global__ void k_set_int(int32_t *out, int32_t v) { *out = v; }
 
 // Dense unit-lower copy of the reflectors of diagonal tile k (block k of the
 // grid): zeros above the diagonal, ones on it, V_kk below.
@@ -1124,7 +1131,7 @@ std::vector<int64_t> serial_order(const TrsmGraph &g);
 
 template <class G, class Body>
 tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, const tqr_options *opt,
-                     hipStream_t stream, int32_t *status_out) {
+                     hipStream_t stream, int32_t *status_out, int status_only_errors = 0) {
     const int64_t nt = g.num_tasks();
     if (nt == 0) return TQR_OK;
     Sched s = sched_at(sched_mem, nt);
@@ -1150,7 +1157,7 @@ tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, 
         }
         HIPCHK(hipGetLastError());
         if (opt && opt->event_end) HIPCHK(hipEventRecord((hipEvent_t)opt->event_end, stream));
-        if (status_out) HIPCHK(hipMemsetAsync(status_out, 0, sizeof(int32_t), stream));
+        if (status_out) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, status_out, 0);
         return TQR_OK;
     }
     const int blocks_init = (int)cdiv(std::max<int64_t>(nt, kMaxWorkers), 256);
@@ -1170,7 +1177,7 @@ tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, 
     hipLaunchKernelGGL(kp, dim3((unsigned)workers), dim3(NT), lds, stream, g, body, s, ro);
     HIPCHK(hipGetLastError());
     if (opt && opt->event_end) HIPCHK(hipEventRecord((hipEvent_t)opt->event_end, stream));
-    if (status_out) hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, stream, s.st, status_out);
+    if (status_out) hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, stream, s.st, status_out, status_only_errors);
     HIPCHK(hipGetLastError());
     return TQR_OK;
 }
@@ -1239,7 +1246,9 @@ tqr_status factor_impl(int64_t m, int64_t n, double *A, int64_t lda, double *T, 
 
 template <int B, int IB>
 tqr_status apply_impl(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *T, double *W, const double *Vd,
-                      double *Bm, int64_t ldb, double *Bt, void *sched, hipStream_t stream) {
+                      double *Bm, int64_t ldb, double *Bt, void *sched, hipStream_t stream,
+                      const tqr_options *opt = nullptr) {
+    int32_t *status = opt ? opt->status : nullptr;
     const int64_t p = cdiv(m, B), q = cdiv(n, B), wb = wb_of(nrhs);
     hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)p, 1), dim3(256), 0, stream, Bm, ldb, m, nrhs, Bt, (int)p, B,
                        (int)wb);
@@ -1247,18 +1256,20 @@ tqr_status apply_impl(bool trans, int64_t m, int64_t n, int64_t nrhs, const doub
     tqr_status st;
     if (trans)
         st = run_graph(g, ApplyBody<B, IB, true>{W, T, Vd, Bt, (int)p, (int)wb}, sched, TileKernels<B, IB>::LDS_BYTES,
-                       nullptr, stream, nullptr);
+                       opt, stream, status, 1);
     else
         st = run_graph(g, ApplyBody<B, IB, false>{W, T, Vd, Bt, (int)p, (int)wb}, sched, TileKernels<B, IB>::LDS_BYTES,
-                       nullptr, stream, nullptr);
+                       opt, stream, status, 1);
     return st;
 }
 
 template <int B>
-tqr_status trsm_impl(int64_t m, int64_t n, int64_t nrhs, const double *W, double *Bt, void *sched, hipStream_t stream) {
+tqr_status trsm_impl(int64_t m, int64_t n, int64_t nrhs, const double *W, double *Bt, void *sched, hipStream_t stream,
+                     const tqr_options *opt = nullptr) {
     const int64_t p = cdiv(m, B), q = cdiv(n, B), wb = wb_of(nrhs);
     TrsmGraph g(q);
-    return run_graph(g, TrsmBody<B>{W, Bt, (int)p, (int)wb, n}, sched, (size_t)B * 16 * 8, nullptr, stream, nullptr);
+    return run_graph(g, TrsmBody<B>{W, Bt, (int)p, (int)wb, n}, sched, (size_t)B * 16 * 8, opt, stream,
+                     opt ? opt->status : nullptr, 1);
 }
 
 template <class F>
@@ -1400,6 +1411,21 @@ tqr_status tqr_form_q(int64_t m, int64_t n, const double *A, int64_t lda, const 
 
 tqr_status tqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb, int tile_b,
                         int inner_ib, double *T, void *work, int64_t work_bytes, int32_t *d_info, hipStream_t stream) {
+    return tqr_solve_ls_ex(m, n, nrhs, A, lda, B, ldb, tile_b, inner_ib, T, work, work_bytes, d_info, stream, nullptr);
+}
+
+tqr_status tqr_solve_ls_ex(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb,
+                           int tile_b, int inner_ib, double *T, void *work, int64_t work_bytes, int32_t *d_info,
+                           hipStream_t stream, const tqr_options *options) {
+    // the three phases share the worker count, wait bound, abort flag and
+    // status; the events bracket the whole solve; no per-task trace
+    tqr_options o{};
+    if (options) {
+        o = *options;
+        o.trace = nullptr;
+        o.event_begin = o.event_end = nullptr;
+    }
+    const tqr_options *po = options ? &o : nullptr;
     if (m < 0 || m < n) return set_err(-1, "m must be >= max(n, 0)");
     if (n < 0) return set_err(-2, "n must be >= 0");
     if (nrhs < 0) return set_err(-3, "nrhs must be >= 0");
@@ -1415,8 +1441,14 @@ tqr_status tqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t l
     if (m > 0 && n > 0 && work_bytes < tqr_workspace_bytes(m, n, nrhs, tile_b, inner_ib))
         return set_err(-12, "work_bytes too small");
     if (!d_info) return set_err(-13, "d_info is null");
+    if (options && (options->struct_size != (int32_t)sizeof(tqr_options) || options->mode != TQR_MODE_PERSISTENT))
+        return set_err(-15, "bad options (struct_size, or a mode other than TQR_MODE_PERSISTENT)");
+    if (options && options->event_begin) HIPCHK(hipEventRecord((hipEvent_t)options->event_begin, stream));
     if (m == 0 || n == 0) {
-        HIPCHK(hipMemsetAsync(d_info, 0, sizeof(int32_t), stream));
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_info, 0);
+        if (options && options->status) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, options->status, 0);
+        if (options && options->event_end) HIPCHK(hipEventRecord((hipEvent_t)options->event_end, stream));
+        HIPCHK(hipGetLastError());
         return TQR_OK;
     }
     const Sizes z = sizes_of(m, n, nrhs, tile_b);
@@ -1431,22 +1463,23 @@ tqr_status tqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t l
                            (int)z.p, Bv, Bv);
         FactorGraph g(z.p, z.q, Bv);
         tqr_status s1 = run_graph(g, FactorBody<Bv, Iv>{W, T, Vd, (int)z.p}, sched, TileKernels<Bv, Iv>::LDS_BYTES,
-                                  nullptr, stream, nullptr);
+                                  po, stream, po ? po->status : nullptr);
         if (s1 != TQR_OK) return s1;
         hipLaunchKernelGGL(k_tiles_to_cm, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, W, (int)z.p, Bv,
                            Bv, A, lda, m, n);
         if (nrhs == 0) return TQR_OK;
-        s1 = apply_impl<Bv, Iv>(true, m, n, nrhs, T, W, Vd, B, ldb, Bt, sched, stream);
+        s1 = apply_impl<Bv, Iv>(true, m, n, nrhs, T, W, Vd, B, ldb, Bt, sched, stream, po);
         if (s1 != TQR_OK) return s1;
         hipLaunchKernelGGL(k_diag_info, dim3(1), dim3(256), 0, stream, W, (int)z.p, Bv, n, d_info);
-        s1 = trsm_impl<Bv>(m, n, nrhs, W, Bt, sched, stream);
+        s1 = trsm_impl<Bv>(m, n, nrhs, W, Bt, sched, stream, po);
         if (s1 != TQR_OK) return s1;
         hipLaunchKernelGGL(k_tiles_to_cm, dim3((unsigned)z.p, 1), dim3(256), 0, stream, Bt, (int)z.p, Bv,
                            (int)wb_of(nrhs), B, ldb, m, nrhs);
         return TQR_OK;
     });
     if (st != TQR_OK) return st;
-    if (nrhs == 0) HIPCHK(hipMemsetAsync(d_info, 0, sizeof(int32_t), stream));
+    if (nrhs == 0) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_info, 0);
+    if (options && options->event_end) HIPCHK(hipEventRecord((hipEvent_t)options->event_end, stream));
     HIPCHK(hipGetLastError());
     return TQR_OK;
 }

@@ -1,0 +1,209 @@
+"""Serving loop for least-squares requests on one GPU (continuous batching).
+
+Requests (A, B) arrive over time, each asking for min ||A X - B|| with FP64
+answers.  The loop admits an arrived request as soon as a slot (a HIP stream)
+is free and the device memory it needs fits in the HBM budget, so the work of
+requests that arrive while others run overlaps on the GPU; every admitted
+request runs ``tqr_solve_ls_ex`` (factor, Q^T B, back substitution) on its own
+stream with a worker count sized to the problem.  Latency is completion time
+minus arrival time on the host's monotonic clock, queueing included.
+
+The admission and bookkeeping core (``Scheduler``) does not touch the GPU;
+``GpuExecutor`` is the HIP side.  The factorisation is bitwise independent of
+the schedule, so a request's answer is the same alone and in the mix.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+from typing import Callable
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# Problem-size rules
+# ---------------------------------------------------------------------------
+
+def tiling_for(m: int, n: int) -> tuple[int, int]:
+    """Tile size and inner block for an m x n solve: the largest tile whose
+    grid still has enough tiles for the device (a size-bucket table)."""
+    if n >= 2048:
+        return 256, 16
+    if n >= 512:
+        return 128, 16
+    if n >= 64:
+        return 64, 16
+    return 32, 16
+
+
+def workers_for(m: int, n: int, tile_b: int, device_slots: int) -> int:
+    """Persistent workgroups for one solve: about one per tile-column strip
+    of the trailing matrix (more would only wait), at most the device."""
+    p, q = -(-m // tile_b), -(-n // tile_b)
+    strips = max(1, tile_b // 64)
+    return int(max(4, min(device_slots, p * q * strips)))
+
+
+def footprint_bytes(m: int, n: int, nrhs: int, tile_b: int, inner_ib: int, work_bytes: int, t_elems: int) -> int:
+    """Device bytes one request holds while in flight: A, B, T, the workspace
+    and the info word."""
+    return 8 * (m * n + m * nrhs + t_elems) + work_bytes + 256
+
+
+# ---------------------------------------------------------------------------
+# Admission core (no GPU)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    t_arrive: float          # seconds after the start of the run
+    m: int
+    n: int
+    nrhs: int
+    footprint: int = 0       # device bytes, set by the executor
+    payload: object = None   # executor data (host buffers)
+
+
+@dataclasses.dataclass
+class Completion:
+    rid: int
+    t_arrive: float
+    t_admit: float
+    t_done: float
+    result: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrive
+
+
+class Scheduler:
+    """FIFO admission by slots and HBM footprint.
+
+    ``launch(req, slot)`` starts a request and returns a handle;
+    ``poll(handle)`` returns None while it runs, else its result.  A request
+    larger than the whole budget is still admitted when nothing else is in
+    flight (it could never run otherwise)."""
+
+    def __init__(self, slots: int, hbm_budget: int, launch: Callable, poll: Callable,
+                 clock: Callable[[], float] = time.perf_counter, idle: Callable[[float], None] | None = None):
+        self.slots, self.budget = slots, hbm_budget
+        self.launch, self.poll, self.clock = launch, poll, clock
+        self.idle = idle or (lambda dt: time.sleep(min(dt, 2e-4)))
+        self.peak_bytes = 0
+        self.peak_inflight = 0
+
+    def run(self, requests: list[Request]) -> list[Completion]:
+        pending = collections.deque(sorted(requests, key=lambda r: r.t_arrive))
+        waiting: collections.deque[Request] = collections.deque()
+        inflight: dict[int, tuple[Request, object, float]] = {}
+        free_slots = list(range(self.slots))[::-1]
+        used = 0
+        done: list[Completion] = []
+        t0 = self.clock()
+        while pending or waiting or inflight:
+            now = self.clock() - t0
+            while pending and pending[0].t_arrive <= now:
+                waiting.append(pending.popleft())
+            progressed = False
+            for slot in list(inflight):
+                req, handle, t_admit = inflight[slot]
+                res = self.poll(handle)
+                if res is not None:
+                    done.append(Completion(req.rid, req.t_arrive, t_admit, self.clock() - t0, res))
+                    del inflight[slot]
+                    free_slots.append(slot)
+                    used -= req.footprint
+                    progressed = True
+            while waiting and free_slots and (used + waiting[0].footprint <= self.budget or not inflight):
+                req = waiting.popleft()
+                slot = free_slots.pop()
+                handle = self.launch(req, slot)
+                used += req.footprint
+                inflight[slot] = (req, handle, self.clock() - t0)
+                self.peak_bytes = max(self.peak_bytes, used)
+                self.peak_inflight = max(self.peak_inflight, len(inflight))
+                progressed = True
+            if not progressed:
+                nxt = pending[0].t_arrive - (self.clock() - t0) if (pending and not waiting and not inflight) else 0.0
+                self.idle(max(nxt, 0.0))
+        return done
+
+
+def latency_stats(done: list[Completion], t_span: float | None = None) -> dict:
+    lat = np.array(sorted(c.latency for c in done))
+    if lat.size == 0:
+        return {}
+    span = t_span if t_span is not None else max(c.t_done for c in done) - min(c.t_arrive for c in done)
+    return {"count": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat[-1] * 1e3),
+            "solves_per_s": float(lat.size / span) if span > 0 else math.inf}
+
+
+# ---------------------------------------------------------------------------
+# GPU executor
+# ---------------------------------------------------------------------------
+
+class GpuExecutor:
+    """Runs requests on HIP streams with the tqr library.  Host data live in
+    pinned buffers, so the copies in and out are asynchronous on the
+    request's stream."""
+
+    def __init__(self, slots: int, device: str = "cuda"):
+        import torch
+        from . import tqr
+        self.torch, self.tqr = torch, tqr
+        self.device = device
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
+        props = torch.cuda.get_device_properties(device)
+        self.device_slots = int(props.multi_processor_count)
+
+    def prepare(self, req: Request, A: np.ndarray, B: np.ndarray) -> Request:
+        """Pins the request's host data and sets its footprint."""
+        torch, tqr = self.torch, self.tqr
+        m, n = A.shape
+        nrhs = B.shape[1]
+        b, ib = tiling_for(m, n)
+        # column-major pinned host copies (a transposed row-major tensor)
+        Ah = torch.empty((n, m), dtype=torch.float64, pin_memory=True)
+        Ah.copy_(torch.from_numpy(np.ascontiguousarray(A.T)))
+        Bh = torch.empty((nrhs, m), dtype=torch.float64, pin_memory=True)
+        Bh.copy_(torch.from_numpy(np.ascontiguousarray(B.T)))
+        Xh = torch.empty((nrhs, n), dtype=torch.float64, pin_memory=True)
+        info_h = torch.empty(1, dtype=torch.int32, pin_memory=True)
+        wb = tqr.workspace_bytes(m, n, nrhs, b, ib)
+        te = tqr.t_elems(m, n, b, ib)
+        req.footprint = footprint_bytes(m, n, nrhs, b, ib, wb, te)
+        req.payload = {"A": Ah, "B": Bh, "X": Xh, "info": info_h, "tile": (b, ib)}
+        return req
+
+    def launch(self, req: Request, slot: int):
+        torch, tqr = self.torch, self.tqr
+        pl = req.payload
+        b, ib = pl["tile"]
+        s = self.streams[slot]
+        with torch.cuda.stream(s):
+            dA = pl["A"].to(self.device, non_blocking=True).t()       # m x n column-major
+            dB = pl["B"].to(self.device, non_blocking=True).t()       # m x nrhs column-major
+            ws = tqr.Workspace(req.m, req.n, req.nrhs, b, ib, self.device)
+            info = torch.zeros(1, dtype=torch.int32, device=self.device)
+            w = workers_for(req.m, req.n, b, self.device_slots)
+            tqr.solve_ls(dA, dB, b, ib, ws, workgroups=w, info=info)
+            pl["X"].copy_(dB[: req.n].t(), non_blocking=True)
+            pl["info"].copy_(info, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        # keep the device tensors alive until the event has passed
+        return {"event": ev, "keep": (dA, dB, ws, info), "payload": pl}
+
+    def poll(self, handle):
+        """None while the request runs; then {"X": nrhs x n pinned host
+        tensor, "info": the dgels-style info word}."""
+        if not handle["event"].query():
+            return None
+        handle["keep"] = None
+        return {"X": handle["payload"]["X"], "info": handle["payload"]["info"]}

@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
         L.tqr_form_q.restype = i32
         L.tqr_solve_ls.argtypes = [i64, i64, i64, dp, i64, dp, i64, i32, i32, dp, vp, i64, vp, vp]
         L.tqr_solve_ls.restype = i32
+        L.tqr_solve_ls_ex.argtypes = [i64, i64, i64, dp, i64, dp, i64, i32, i32, dp, vp, i64, vp, vp, ctypes.POINTER(Options)]
+        L.tqr_solve_ls_ex.restype = i32
         L.tqr_last_error_string.argtypes = []
         L.tqr_last_error_string.restype = ctypes.c_char_p
         L.tqr_graph_tasks.argtypes = [i64, i64, i32]
@@ -184,17 +186,28 @@ def form_q(A, T, tile_b, inner_ib, Q: torch.Tensor | None = None, ws: Workspace 
     return Q
 
 
-def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None):
+def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None, *, workgroups: int = 0,
+             status: torch.Tensor | None = None, info: torch.Tensor | None = None):
     """min ||A X - B||: A overwritten by its factors, X in B[0:n].  Returns
-    (B, info tensor on the device)."""
+    (B, info tensor on the device).  ``workgroups`` > 0 caps the persistent
+    workers of every phase (tqr_solve_ls_ex)."""
     m, n = A.shape
     nrhs = B.shape[1]
     if ws is None:
         ws = Workspace(m, n, nrhs, tile_b, inner_ib, A.device)
-    info = torch.zeros(1, dtype=torch.int32, device=A.device)
-    rc = lib().tqr_solve_ls(m, n, nrhs, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), tile_b, inner_ib,
-                            ws.T.data_ptr(), ws.work.data_ptr(), ws.work.numel(), info.data_ptr(), _stream())
-    _check("tqr_solve_ls", rc)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    if workgroups > 0 or status is not None:
+        opt = Options(ctypes.sizeof(Options), workgroups, MODE_PERSISTENT, POLICY_PAPER, None, None,
+                      status.data_ptr() if status is not None else None, 0, None, None)
+        rc = lib().tqr_solve_ls_ex(m, n, nrhs, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), tile_b, inner_ib,
+                                   ws.T.data_ptr(), ws.work.data_ptr(), ws.work.numel(), info.data_ptr(), _stream(),
+                                   ctypes.byref(opt))
+        _check("tqr_solve_ls_ex", rc)
+    else:
+        rc = lib().tqr_solve_ls(m, n, nrhs, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), tile_b, inner_ib,
+                                ws.T.data_ptr(), ws.work.data_ptr(), ws.work.numel(), info.data_ptr(), _stream())
+        _check("tqr_solve_ls", rc)
     return B, info
 
 

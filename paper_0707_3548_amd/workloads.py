@@ -106,14 +106,21 @@ def random_orthogonal_factor(m: int, k: int, g: np.random.Generator, reflectors:
     return Q[perm]
 
 
-def ls_request(m: int, n: int, nrhs: int, cond: float, seed: int, noise: float = 1e-6):
-    """One serving request: A = U diag(s) V^T with U, V from a few random
-    reflectors (exact singular values s), b = A x + noise."""
+def ls_request(m: int, n: int, nrhs: int, cond: float, seed: int, noise: float = 1e-6, reflectors: int = 4):
+    """One serving request: A = U diag(s) V^T with exact singular values s,
+    U = P H_r .. H_1 [I; 0] (the construction of random_orthogonal_factor)
+    and V from a few reflectors as well; b = A x + noise.  The reflectors act
+    directly on [diag(s) V^T; 0], so building A costs O(m n) per reflector."""
     gu, gv, gx, gn = _streams(seed, 4)
-    U = random_orthogonal_factor(m, n, gu)
-    V = random_orthogonal_factor(n, n, gv)
+    V = random_orthogonal_factor(n, n, gv, reflectors)
     s = singular_values(n, cond)
-    A = np.asfortranarray((U * s[None, :]) @ V.T)
+    M = np.zeros((m, n))
+    M[:n] = s[:, None] * V.T
+    for _ in range(reflectors):
+        u = gu.standard_normal(m)
+        u /= np.linalg.norm(u)
+        M -= 2.0 * np.outer(u, u @ M)
+    A = np.asfortranarray(M[gu.permutation(m)])
     x = gx.standard_normal((n, nrhs))
     b = np.asfortranarray(A @ x + noise * gn.standard_normal((m, nrhs)))
     return A, b, x

@@ -91,3 +91,15 @@ def test_form_q_argument_checks(lib):
     assert lib.tqr_form_q(8, 8, fake, 8, fake, 64, 16, fake, 8, None, big, None) == -10
     assert lib.tqr_form_q(8, 8, fake, 8, fake, 64, 16, fake, 8, fake, 16, None) == -11
     assert lib.tqr_form_q(0, 0, None, 1, None, 64, 16, None, 1, None, 0, None) == 0
+
+
+def test_solve_ls_ex_option_checks(lib):
+    from paper_0707_3548_amd import tqr
+    fake = ctypes.c_void_p(256)
+    big = 1 << 40
+    bad = tqr.Options(ctypes.sizeof(tqr.Options) - 8, 0, 0, 0, None, None, None, 0, None, None)
+    assert lib.tqr_solve_ls_ex(8, 8, 1, fake, 8, fake, 8, 64, 16, fake, fake, big, fake, None, ctypes.byref(bad)) == -15
+    serial = tqr.Options(ctypes.sizeof(tqr.Options), 0, tqr.MODE_SERIAL, 0, None, None, None, 0, None, None)
+    assert lib.tqr_solve_ls_ex(8, 8, 1, fake, 8, fake, 8, 64, 16, fake, fake, big, fake, None, ctypes.byref(serial)) == -15
+    # earlier arguments are reported first
+    assert lib.tqr_solve_ls_ex(8, 9, 1, fake, 8, fake, 8, 64, 16, fake, fake, big, fake, None, ctypes.byref(bad)) == -1
