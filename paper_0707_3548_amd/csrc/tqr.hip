@@ -211,18 +211,56 @@ __device__ int32_t try_pop(const Sched &s, uint64_t deadline, uint32_t &spins, i
     return -1;
 }
 
+__device__ __forceinline__ bool queue_has_level_below(const Sched &s, int lvl) {
+    for (int l = 0; l < lvl; ++l) {
+        const uint64_t w = flag_load(&s.st->ht[l]);
+        if ((uint32_t)w < (uint32_t)(w >> 32)) return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ void push_one(const Sched &s, int lvl, int32_t t) {
+    const uint32_t pos = (uint32_t)(__hip_atomic_fetch_add(&s.st->ht[lvl], 1ull << 32, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) >> 32);
+    __hip_atomic_store(&s.queue[lvl * s.cap + pos], t, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+}
+
+__device__ void wake_idle(const Sched &s, int count, int nworkers);
+
+// Clears this worker's idle bit.  Returns kMboxEmpty when the bit was still
+// set.  Otherwise another worker claimed this one first and is writing its
+// mailbox: the message (a task id, kMboxWake or kMboxStop) is waited for,
+// taken out and returned.
+__device__ int32_t withdraw_idle(const Sched &s, uint64_t *word, uint64_t bit, int32_t *mb, uint64_t deadline,
+                                 uint32_t &spins, int nworkers) {
+    const uint64_t old = __hip_atomic_fetch_and(word, ~bit, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+    if (old & bit) return kMboxEmpty;
+    while (flag_load(mb) == kMboxEmpty) {
+        if (rt_clock() > deadline || ++spins > kMaxSpins) {
+            abort_run(s, nworkers);
+            return kMboxStop;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return __hip_atomic_exchange(mb, kMboxEmpty, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+}
+
 // Thread 0 of an idle worker: returns the next task, or -1 when the graph is
 // finished or aborted.  An idle worker sets its bit in the idle bitmap, looks
-// at the queues once more, and then polls only its own mailbox.  A worker
-// that publishes tasks pushes them first and then wakes idle workers; with a
-// sequentially consistent fence between the write and the read on both sides
-// (bit set -> queue look; push -> bitmap look), a task published while a
-// worker goes idle is seen by one of the two, so no task is left in a queue
-// while every worker waits.  Waits are bounded by the deadline and a spin
-// count; the periodic check of the done count, the status and the abort flag
-// also ends a wait.
-__device__ int32_t idle_wait(const Sched &s, uint32_t nsinks, const volatile int32_t *abort_flag, uint64_t deadline,
-                             int me, int nworkers) {
+// at the queues once more, and then polls only its own mailbox, where a
+// worker that releases tasks either hands one over directly (its id) or
+// leaves a wake-up (look at the queues).  A worker that publishes tasks
+// hands them to claimed idle workers or pushes them and then wakes idle
+// workers; with a sequentially consistent fence between the write and the
+// read on both sides (bit set -> queue look; push -> bitmap look), a task
+// published while a worker goes idle is seen by one of the two, so no task is
+// left in a queue while every worker waits.  A sleeping worker also looks at
+// the queues every 64 polls (a queue word can be contended enough that a
+// woken worker loses every exchange for a while).  Waits are bounded by the
+// deadline and a spin count; the periodic check of the done count, the
+// status and the abort flag also ends a wait.
+template <class G>
+__device__ int32_t idle_wait(const G &g, int policy, const Sched &s, uint32_t nsinks,
+                             const volatile int32_t *abort_flag, uint64_t deadline, int me, int nworkers) {
     uint32_t spins = 0;
     uint64_t *word = &s.st->idle[me >> 6];
     const uint64_t bit = 1ull << (me & 63);
@@ -236,9 +274,15 @@ __device__ int32_t idle_wait(const Sched &s, uint32_t nsinks, const volatile int
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
         t = try_pop(s, deadline, spins, nworkers);
         if (t >= 0) {
-            // withdraw; if a waker cleared the bit first, its wake-up stays
-            // in the mailbox and only costs one extra look later
-            __hip_atomic_fetch_and(word, ~bit, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+            const int32_t m = withdraw_idle(s, word, bit, mb, deadline, spins, nworkers);
+            if (m >= 0) {
+                // a task handed over while this worker took one itself goes
+                // back to the queues
+                push_one(s, level_of(g, g.decode(m), policy), m);
+                wake_idle(s, 1, nworkers);
+            } else if (m == kMboxStop) {
+                __hip_atomic_store(mb, kMboxStop, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+            }
             return t;
         }
         if (t == -2) return -1;
@@ -247,6 +291,7 @@ __device__ int32_t idle_wait(const Sched &s, uint32_t nsinks, const volatile int
             if (flag_load(mb) != kMboxEmpty) {
                 const int32_t v = __hip_atomic_exchange(mb, kMboxEmpty, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
                 if (v == kMboxStop) return -1;
+                if (v >= 0) return v;        // handed over
                 if (v != kMboxEmpty) break;  // woken: look at the queues
             }
             if ((++polls & 63) == 0) {
@@ -254,6 +299,12 @@ __device__ int32_t idle_wait(const Sched &s, uint32_t nsinks, const volatile int
                 if ((abort_flag && flag_load(const_cast<const int32_t *>(abort_flag))) || rt_clock() > deadline) {
                     abort_run(s, nworkers);
                     return -1;
+                }
+                if (queue_has_level_below(s, kLevels)) {
+                    const int32_t m = withdraw_idle(s, word, bit, mb, deadline, spins, nworkers);
+                    if (m >= 0) return m;
+                    if (m == kMboxStop) return -1;
+                    break;
                 }
             }
             if (++spins > kMaxSpins) {
@@ -263,6 +314,59 @@ __device__ int32_t idle_wait(const Sched &s, uint32_t nsinks, const volatile int
             __builtin_amdgcn_s_sleep(4);
         }
     }
+}
+
+// Thread 0 with ready tasks to publish (ready[r] for the r with lvl[r] >= 0,
+// taken in level order): claims idle workers in the bitmap and writes one
+// task id into each one's mailbox; a handed-over task gets lvl[r] = -1.  A
+// mailbox that is not empty (a message not yet taken) keeps its task for the
+// queues.  Returns the number handed over.
+__device__ int handoff_ready(const Sched &s, const int32_t *ready, int8_t *lvl, int nr, int nworkers) {
+    int left = 0;
+    for (int r = 0; r < nr; ++r) left += lvl[r] >= 0;
+    if (left == 0) return 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    int handed = 0, cur_lvl = 0, cur_r = 0;
+    // next task in priority order (level, then position); -1 when none left
+    auto next_task = [&]() -> int {
+        for (; cur_lvl < kLevels; ++cur_lvl, cur_r = 0)
+            for (; cur_r < nr; ++cur_r)
+                if (lvl[cur_r] == cur_lvl) return cur_r;
+        return -1;
+    };
+    const int nwords = (nworkers + 63) >> 6;
+    for (int wi = 0; wi < nwords && left > 0; ++wi) {
+        uint64_t v = flag_load(&s.st->idle[wi]);
+        while (v != 0 && left > 0) {
+            uint64_t mask = 0, rest = v;
+            for (int c = 0; c < left && rest != 0; ++c) {
+                const uint64_t low = rest & (~rest + 1);
+                mask |= low;
+                rest &= rest - 1;
+            }
+            const uint64_t old = __hip_atomic_fetch_and(&s.st->idle[wi], ~mask, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+            uint64_t got = old & mask;
+            while (got != 0) {
+                const int w = (wi << 6) + __builtin_ctzll(got);
+                got &= got - 1;
+                const int r = next_task();
+                int32_t expect = kMboxEmpty;
+                if (r >= 0 && __hip_atomic_compare_exchange_strong(&s.mbox[w * kMboxStride], &expect, ready[r],
+                                                                   __ATOMIC_RELAXED, __ATOMIC_RELAXED, TQR_FLAG_SCOPE)) {
+                    lvl[r] = -1;
+                    ++handed;
+                    --left;
+                } else if (r < 0) {
+                    // more workers claimed than tasks left (cannot happen
+                    // with one claimer per word, kept for safety): wake it
+                    __hip_atomic_compare_exchange_strong(&s.mbox[w * kMboxStride], &expect, kMboxWake,
+                                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+                }
+            }
+            v = old & ~mask;
+        }
+    }
+    return handed;
 }
 
 // Thread 0 after pushing `count` tasks: wakes up to `count` idle workers.
@@ -345,6 +449,7 @@ struct TileKernels {
     static constexpr int STAGE_V = B * IB / NT;               // V doubles per thread per block
     static constexpr int STAGE_T = (IB * IB + NT - 1) / NT;   // T doubles per thread per block
     static constexpr int RPL = B >= 64 ? B / 64 : 1;        // panel rows per lane (one-wave panels)
+    static constexpr int PU = 4;                            // column steps unrolled per group in the panels
 
     // A strip (matrix-core accumulator layout) into LDS as Vl[c * LDV + r].
     __device__ __forceinline__ static void strip_to_lds(const Strip<B> &C, double *Vl) {
@@ -421,7 +526,7 @@ struct TileKernels {
 #pragma unroll
             for (int c = 0; c < 16; ++c) x[i][c] = r < B ? Vn[c * LDV + r] : 0.0;
         }
-        ge_panel16<RPL>(x, Tn, Pl);
+        ge_panel16u<RPL, PU>(x, Tn, Pl);
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int rr = l + 64 * i, r = cj + rr;
@@ -486,10 +591,10 @@ struct TileKernels {
             strip_to_lds(C, Vn);
         }
         // the diagonal block of R (upper triangle), row-major with row r
-        // rotated left by r (the layout ts_panel16 works in)
+        // rotated left by panel_rot(r) (the layout ts_panel16u works in)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int idx = l + 64 * q, r = idx >> 4, c = (r + (idx & 15)) & 15;
+            const int idx = l + 64 * q, r = idx >> 4, c = (panel_rot<PU>(r) + (idx & 15)) & 15;
             Rd[idx] = r <= c ? rcol[(size_t)c * B + cj + r] : 0.0;
         }
         double x[RPL][16];
@@ -499,7 +604,7 @@ struct TileKernels {
 #pragma unroll
             for (int c = 0; c < 16; ++c) x[i][c] = r < B ? Vn[c * LDV + r] : 0.0;
         }
-        ts_panel16<RPL>(x, Rd, Tn, Rd + 256);
+        ts_panel16u<RPL, PU>(x, Rd, Tn, Rd + 256);
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int r = l + 64 * i;
@@ -513,7 +618,7 @@ struct TileKernels {
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int idx = l + 64 * q, r = idx >> 4, c = (r + (idx & 15)) & 15;
+            const int idx = l + 64 * q, r = idx >> 4, c = (panel_rot<PU>(r) + (idx & 15)) & 15;
             if (r <= c) rcol[(size_t)c * B + cj + r] = Rd[idx];
             Tik[(size_t)cj * 16 + idx] = Tn[idx];
         }
@@ -875,19 +980,6 @@ struct TrsmBody {
 // highest-priority ready task, runs it, and releases its successors; a
 // successor whose last dependency is released is pushed on its level's queue.
 // ===========================================================================
-__device__ __forceinline__ bool queue_has_level_below(const Sched &s, int lvl) {
-    for (int l = 0; l < lvl; ++l) {
-        const uint64_t w = flag_load(&s.st->ht[l]);
-        if ((uint32_t)w < (uint32_t)(w >> 32)) return true;
-    }
-    return false;
-}
-
-__device__ __forceinline__ void push_one(const Sched &s, int lvl, int32_t t) {
-    const uint32_t pos = (uint32_t)(__hip_atomic_fetch_add(&s.st->ht[lvl], 1ull << 32, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) >> 32);
-    __hip_atomic_store(&s.queue[lvl * s.cap + pos], t, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
-}
-
 constexpr int kReadyCap = 64;  // ready successors collected per task before publishing
 
 template <class G, class Body>
@@ -911,7 +1003,8 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
             if (next >= 0 && flag_load(&s.st->status) != 0) next = -1;
             s_cont = next >= 0;
             s_task = next >= 0 ? next
-                               : idle_wait(s, nsinks, o.abort_flag, rt_clock() + (uint64_t)o.timeout, blockIdx.x, nworkers);
+                               : idle_wait(g, o.policy, s, nsinks, o.abort_flag, rt_clock() + (uint64_t)o.timeout,
+                                           blockIdx.x, nworkers);
             s_nready = 0;
             s_nover = 0;
         }
@@ -979,6 +1072,10 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
                 }
             }
             if (best >= 0 && queue_has_level_below(s, best_lvl)) best = -1;
+            // the continuation is not published; the rest go to idle
+            // workers first (highest priority first), then to the queues
+            if (best >= 0) s_lvl[best] = -1;
+            handoff_ready(s, s_ready, s_lvl, nr, nworkers);
             int pushed = s_nover;
             for (int l = 0; l < kLevels; ++l) {
                 int c = 0;

@@ -569,4 +569,244 @@ __device__ __forceinline__ void ge_panel16(double (&x)[RPL][16], double *Tl, dou
     panel_t_from_gram(Gs, taus, Tl);
 }
 
+// ---------------------------------------------------------------------------
+// Unrolled one-wave panels.  The 16 column steps run in groups of U
+// (U = 4, 8 or 16) with the step inside a group a compile-time constant, so
+// the pivot, the columns right of it and the columns holding earlier
+// reflectors are known statically and the columns rotate left by U only
+// after each group (not at all for U = 16).  Relative column c of group g is
+// panel column (c + U g) mod 16.  Compared with the rotating panels above:
+// the row of R that TSQRT updates is added into the batched products by the
+// lanes of the first quarter (so the reduction yields w = R row + v^T A
+// directly), the update is x -= w (tau v) on the live columns only, and the
+// reflector takes one division.
+// ---------------------------------------------------------------------------
+
+// beta = -sgn(alpha) sqrt(alpha^2 + sigma2), d = alpha - beta (no
+// cancellation: |d| = |alpha| + |beta|), q = 1 / (beta d): 1/beta = d q and
+// 1/d = beta q, so tau = (beta - alpha) / beta = -d^2 q and scale = beta q.
+__device__ __forceinline__ Reflector make_reflector_1div(double alpha, double sigma2) {
+    Reflector h{0.0, alpha, 1.0};
+    if (sigma2 != 0.0) {
+        const double nrm = sqrt(fma(alpha, alpha, sigma2));
+        h.beta = alpha >= 0.0 ? -nrm : nrm;
+        const double d = alpha - h.beta;
+        const double q = 1.0 / (h.beta * d);
+        h.tau = -(d * d) * q;
+        h.scale = h.beta * q;
+    }
+    return h;
+}
+
+// Rotation (in columns) in force at step r of a panel unrolled by U.
+template <int U>
+__device__ __forceinline__ int panel_rot(int r) { return (r / U) * U & 15; }
+
+template <int RPL, int U>
+__device__ __forceinline__ void rotate_left_by(double (&x)[RPL][16]) {
+    if constexpr (U < 16) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            double t[U];
+#pragma unroll
+            for (int c = 0; c < U; ++c) t[c] = x[i][c];
+#pragma unroll
+            for (int c = 0; c + U < 16; ++c) x[i][c] = x[i][c + U];
+#pragma unroll
+            for (int c = 0; c < U; ++c) x[i][16 - U + c] = t[c];
+        }
+    }
+}
+
+// Batched products of one step: lane l ends with P[c] = add(c) + sum over
+// the wave of v . x[.][c] for every c (the same in all lanes), where add(c)
+// is the value lane c (< 16) passes in `add`; the totals also go to Gcol.
+// `own` is the total of column l & 15.  SKIP is a column whose product is
+// not needed (its partial is taken as 0).
+template <int RPL, int SKIP>
+__device__ __forceinline__ void panel_products_add(const double (&x)[RPL][16], const double (&v)[RPL], double add,
+                                                   double (&P)[16], double &own, double *part, double *Gcol) {
+    const int l = lane_id();
+    double pv[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        double acc = 0.0;
+        if (c != SKIP) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) acc = fma(v[i], x[i][c], acc);
+        }
+        pv[c] = acc;
+    }
+    double2 *row = reinterpret_cast<double2 *>(part + l * kPartStride);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) row[i] = double2{pv[2 * i], pv[2 * i + 1]};
+    const double *col = part + (l >> 4) * 16 * kPartStride + (l & 15);
+    double s4[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) s4[a] = col[a * kPartStride];
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) s4[a] += col[(4 * k + a) * kPartStride];
+    double s = ((s4[0] + s4[1]) + (s4[2] + s4[3])) + add;
+    s = sum_xor32(sum_xor16(s));
+    own = s;
+    if (l < 16) Gcol[l] = s;
+    const double2 *g = reinterpret_cast<const double2 *>(Gcol);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const double2 t = g[i];
+        P[2 * i] = t.x;
+        P[2 * i + 1] = t.y;
+    }
+}
+
+// T from the Gram columns of an unrolled panel: step j stored column j with
+// the rotation of its group, G(d, j) = Gs[16 j + ((d - rot(j)) & 15)].
+template <int U>
+__device__ __forceinline__ void panel_t_from_gram_u(const double *Gs, const double *taus, double *Tl) {
+    const int l = lane_id(), r = l & 15;
+#pragma unroll 1
+    for (int j = 0; j < 16; ++j) {
+        const double tau = taus[j];
+        const int rot = panel_rot<U>(j);
+        const double *g = Gs + 16 * j;
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 15; ++d)
+            if (d < j) acc += Tl[r + 16 * d] * g[(d - rot) & 15];
+        if (l < 16) Tl[l + 16 * j] = l < j ? -tau * acc : (l == j ? tau : 0.0);
+    }
+}
+
+// One step of the unrolled TSQRT panel: step jj = U g + u, pivot in relative
+// column u.  Rr holds the diagonal block of R row-major with row r rotated
+// left by rot(r) (Rr[16 r + c] = R[r][(c + rot(r)) mod 16], zero where that
+// column is left of r).
+template <int RPL, int U, int u>
+__device__ __forceinline__ void ts_step(double (&x)[RPL][16], int g, double *Rr, double *part, double *Gs, double *taus) {
+    const int l = lane_id();
+    const int jj = U * g + u;
+    double *rrow = Rr + 16 * jj;
+    const double alpha = rrow[u];
+    const double radd = l < 16 ? rrow[l] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) s = fma(x[i][u], x[i][u], s);
+    const double sigma2 = wave_sum(s);
+    const Reflector h = make_reflector_1div(alpha, sigma2);
+    double v[RPL], tv[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        v[i] = x[i][u] * h.scale;
+        tv[i] = h.tau * v[i];
+    }
+    double P[16], own;
+    panel_products_add<RPL, u>(x, v, radd, P, own, part, Gs + 16 * jj);
+    // live columns right of the pivot: relative u+1 .. 15 - U g
+    const int last = 15 - U * g;
+    if (l < 16) {
+        const bool right = l > u && l <= last;
+        rrow[l] = right ? fma(-h.tau, own, radd) : (l == u ? h.beta : radd);
+    }
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+        // groups wholly left of the pivot are skipped statically; since U is a
+        // multiple of 4, a group past `last` holds only earlier reflectors
+        if (4 * grp + 3 <= u) continue;
+        if (4 * grp > last) continue;
+#pragma unroll
+        for (int c = 4 * grp; c < 4 * grp + 4; ++c) {
+            if (c <= u) continue;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) x[i][c] = fma(-P[c], tv[i], x[i][c]);
+        }
+    }
+    if (l == 0) taus[jj] = h.tau;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) x[i][u] = v[i];
+}
+
+template <int RPL, int U, int u = 0>
+__device__ __forceinline__ void ts_group(double (&x)[RPL][16], int g, double *Rr, double *part, double *Gs, double *taus) {
+    if constexpr (u < U) {
+        ts_step<RPL, U, u>(x, g, Rr, part, Gs, taus);
+        ts_group<RPL, U, u + 1>(x, g, Rr, part, Gs, taus);
+    }
+}
+
+// DTSQT2 on one inner block, unrolled by U (see ts_panel16 for the roles of
+// x, Tl and scr; Rr in the layout of ts_step).
+template <int RPL, int U>
+__device__ __forceinline__ void ts_panel16u(double (&x)[RPL][16], double *Rr, double *Tl, double *scr) {
+    static_assert(U % 4 == 0 && 16 % U == 0, "U must be 4, 8 or 16");
+    double *part = scr, *Gs = scr + 64 * kPartStride, *taus = Gs + 256;
+#pragma unroll 1
+    for (int g = 0; g < 16 / U; ++g) {
+        ts_group<RPL, U>(x, g, Rr, part, Gs, taus);
+        rotate_left_by<RPL, U>(x);
+    }
+    panel_t_from_gram_u<U>(Gs, taus, Tl);
+}
+
+template <int RPL, int U, int u>
+__device__ __forceinline__ void ge_step(double (&x)[RPL][16], int g, double *part, double *Gs, double *taus) {
+    const int l = lane_id();
+    const int jj = U * g + u;
+    const bool below = l > jj, at = l == jj;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const double t = i == 0 && !below ? 0.0 : x[i][u];
+        s = fma(t, t, s);
+    }
+    const double sigma2 = wave_sum(s);
+    const Reflector h = make_reflector_1div(readlane_d(x[0][u], jj), sigma2);
+    double v[RPL], tv[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        v[i] = i == 0 ? (below ? x[0][u] * h.scale : (at ? 1.0 : 0.0)) : x[i][u] * h.scale;
+        tv[i] = h.tau * v[i];
+    }
+    double P[16], own;
+    panel_products_add<RPL, u>(x, v, 0.0, P, own, part, Gs + 16 * jj);
+    const int last = 15 - U * g;
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+        if (4 * grp + 3 <= u) continue;
+        if (4 * grp > last) continue;
+#pragma unroll
+        for (int c = 4 * grp; c < 4 * grp + 4; ++c) {
+            if (c <= u) continue;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) x[i][c] = fma(-P[c], tv[i], x[i][c]);
+        }
+    }
+    if (l == 0) taus[jj] = h.tau;
+    x[0][u] = below ? v[0] : (at ? h.beta : x[0][u]);
+#pragma unroll
+    for (int i = 1; i < RPL; ++i) x[i][u] = v[i];
+}
+
+template <int RPL, int U, int u = 0>
+__device__ __forceinline__ void ge_group(double (&x)[RPL][16], int g, double *part, double *Gs, double *taus) {
+    if constexpr (u < U) {
+        ge_step<RPL, U, u>(x, g, part, Gs, taus);
+        ge_group<RPL, U, u + 1>(x, g, part, Gs, taus);
+    }
+}
+
+// DGEQT2 on one inner block, unrolled by U (roles as in ge_panel16).
+template <int RPL, int U>
+__device__ __forceinline__ void ge_panel16u(double (&x)[RPL][16], double *Tl, double *scr) {
+    static_assert(U % 4 == 0 && 16 % U == 0, "U must be 4, 8 or 16");
+    double *part = scr, *Gs = scr + 64 * kPartStride, *taus = Gs + 256;
+#pragma unroll 1
+    for (int g = 0; g < 16 / U; ++g) {
+        ge_group<RPL, U>(x, g, part, Gs, taus);
+        rotate_left_by<RPL, U>(x);
+    }
+    panel_t_from_gram_u<U>(Gs, taus, Tl);
+}
+
 }  // namespace tqr
