@@ -425,6 +425,42 @@ struct RunOpts {
     int policy;
 };
 
+// Progress of the chain of tasks that rewrite the triangle R_kk (GEQRT(k),
+// then TSQRT(k+1,k), TSQRT(k+2,k), ...).  Inner block s of these tasks
+// touches only row block s of R_kk (and, for the panel of block s+1 that the
+// lookahead factors, the diagonal block of row block s+1), so a task of the
+// chain can follow its predecessor one row block behind instead of waiting
+// for it to finish: `prev` counts the row blocks of R_kk the predecessor has
+// finished, `mine` the same for this task (null: nothing to wait for, or
+// nobody waiting).  Waits are bounded by `deadline`; a timeout sets *status to
+// TQR_EABORTED and lets the task run on (its results are then void).
+struct Pipe {
+    int32_t *prev, *mine, *status;
+    uint64_t deadline;
+};
+
+// Thread 0: waits until the predecessor has finished `target` row blocks,
+// then acquires its writes.
+__device__ void pipe_wait(const Pipe &pp, int target) {
+    uint32_t n = 0;
+    while (flag_load(pp.prev) < target) {
+        if (flag_load(pp.status) != 0) return;
+        if (rt_clock() > pp.deadline || ++n > kMaxSpins) {
+            __hip_atomic_store(pp.status, (int32_t)TQR_EABORTED, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Thread 0, after a workgroup barrier: releases the workgroup's writes and
+// publishes that `count` row blocks are finished.
+__device__ void pipe_publish(const Pipe &pp, int count) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(pp.mine, count, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+}
+
 // ===========================================================================
 // Tile kernels (bodies run by one workgroup)
 // ===========================================================================
@@ -478,13 +514,15 @@ struct TileKernels {
     // j-1 to it (lookahead), while waves 1..3 apply block j-1 to the columns
     // right of panel j on the matrix cores.  V and T of the last factored
     // block alternate between two LDS buffers; one barrier per block.
-    __device__ __forceinline__ static void geqrt16(double *Akk, double *Tkk, double *Vkk, double *smem) {
+    __device__ __forceinline__ static void geqrt16(double *Akk, double *Tkk, double *Vkk, double *smem, const Pipe &pp) {
         double *Vb[2] = {smem, smem + 16 * LDV};
         double *Tb[2] = {smem + 32 * LDV, smem + 32 * LDV + 256};
         double *Pl = smem + 32 * LDV + 512 + 256;
         const int w = __builtin_amdgcn_readfirstlane(wave_id());
+        const bool t0 = threadIdx.x == 0;
         if (w == 0) geqrt16_panel(Akk, Tkk, Vkk, 0, nullptr, nullptr, Vb[0], Tb[0], Pl);
         __syncthreads();
+        if (NB == 1 && pp.mine && t0) pipe_publish(pp, 1);
 #pragma unroll 1
         for (int s = 0; s + 1 < NB; ++s) {
             double *Vs = Vb[s & 1], *Ts = Tb[s & 1];
@@ -499,6 +537,8 @@ struct TileKernels {
                 }
             }
             __syncthreads();
+            // row block s is final (and so is row block NB-1 after the last block)
+            if (pp.mine && t0) pipe_publish(pp, s + 2 == NB ? NB : s + 1);
         }
     }
 
@@ -555,13 +595,22 @@ struct TileKernels {
     // TSQRT with ib = 16, organised as geqrt16: wave 0 factors [R_kk block;
     // A_ik panel] pairs (ts_panel16) with lookahead, waves 1..3 apply each
     // block to the columns right of the next panel.
-    __device__ __forceinline__ static void tsqrt16(double *Akk, double *Aik, double *Tik, double *smem) {
+    __device__ __forceinline__ static void tsqrt16(double *Akk, double *Aik, double *Tik, double *smem, const Pipe &pp) {
         double *Vb[2] = {smem, smem + 16 * LDV};
         double *Tb[2] = {smem + 32 * LDV, smem + 32 * LDV + 256};
         double *Rd = smem + 32 * LDV + 512;
         const int w = __builtin_amdgcn_readfirstlane(wave_id());
+        const bool t0 = threadIdx.x == 0;
+        // block s (with the lookahead panel s+1) touches row blocks s and s+1
+        // of R_kk: it may start once the predecessor has finished s+2 of them
+        if (pp.prev) {
+            if (t0) pipe_wait(pp, 1);
+            __syncthreads();
+        }
         if (w == 0) tsqrt16_panel(Akk, Aik, Tik, 0, nullptr, nullptr, Vb[0], Tb[0], Rd);
+        if (pp.prev && t0) pipe_wait(pp, min(2, NB));
         __syncthreads();
+        if (NB == 1 && pp.mine && t0) pipe_publish(pp, 1);
 #pragma unroll 1
         for (int s = 0; s + 1 < NB; ++s) {
             double *Vs = Vb[s & 1], *Ts = Tb[s & 1];
@@ -575,7 +624,9 @@ struct TileKernels {
                     strip_store<B>(C, Aik + (size_t)16 * j * B, B);
                 }
             }
+            if (pp.prev && t0) pipe_wait(pp, min(s + 3, NB));
             __syncthreads();
+            if (pp.mine && t0) pipe_publish(pp, s + 2 == NB ? NB : s + 1);
         }
     }
 
@@ -638,9 +689,9 @@ struct TileKernels {
 
     // DGEQT2 (GEQRT): A_kk <- V_kk, R_kk; T_kk written; Vkk receives V_kk as
     // a dense unit-lower matrix for the LARFB tasks.
-    __device__ __forceinline__ static void geqrt(double *Akk, double *Tkk, double *Vkk, double *smem) {
+    __device__ __forceinline__ static void geqrt(double *Akk, double *Tkk, double *Vkk, double *smem, const Pipe &pp) {
         if constexpr (IB == 16) {
-            geqrt16(Akk, Tkk, Vkk, smem);
+            geqrt16(Akk, Tkk, Vkk, smem, pp);
             return;
         }
         Lds L(smem);
@@ -685,9 +736,9 @@ struct TileKernels {
 
     // DTSQT2 (TSQRT): [R_kk; A_ik] <- R~_kk, V_ik; T_ik written.  Only the
     // upper triangle of the diagonal tile is read or written.
-    __device__ __forceinline__ static void tsqrt(double *Akk, double *Aik, double *Tik, double *smem) {
+    __device__ __forceinline__ static void tsqrt(double *Akk, double *Aik, double *Tik, double *smem, const Pipe &pp) {
         if constexpr (IB == 16) {
-            tsqrt16(Akk, Aik, Tik, smem);
+            tsqrt16(Akk, Aik, Tik, smem, pp);
             return;
         }
         Lds L(smem);
@@ -865,14 +916,29 @@ struct FactorBody {
     double *T;   // T slots
     double *Vd;  // dense unit-lower V of each diagonal tile
     int p;
+    // pipelined R_kk chain (inner block 16, persistent mode): progress word
+    // of chain task (i,k) at prog[k*p + i]; null runs every chain task only
+    // after its predecessor has finished
+    int32_t *prog = nullptr;
+    int32_t *status = nullptr;
+    int64_t wait_ticks = 0;
     __device__ double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
+    __device__ Pipe pipe(const Task &t) const {
+        Pipe pp{nullptr, nullptr, status, 0};
+        if (prog) {
+            if (t.kind == TSQRT) pp.prev = prog + (int64_t)t.k * p + t.i - 1;
+            if (t.i + 1 < p) pp.mine = prog + (int64_t)t.k * p + t.i;
+            pp.deadline = rt_clock() + (uint64_t)wait_ticks;
+        }
+        return pp;
+    }
     __device__ double *tslot(int i, int k) const { return T + ((int64_t)k * p + i) * IB * B; }
     __device__ double *vdiag(int k) const { return Vd + (int64_t)k * B * B; }
     __device__ __forceinline__ void run(const Task &t, double *smem) const {
         const int cbeg = t.c * kStripCols, cend = min(B, cbeg + kStripCols);
         switch (t.kind) {
-        case GEQRT: K::geqrt(tile(t.k, t.k), tslot(t.k, t.k), vdiag(t.k), smem); break;
-        case TSQRT: K::tsqrt(tile(t.k, t.k), tile(t.i, t.k), tslot(t.i, t.k), smem); break;
+        case GEQRT: K::geqrt(tile(t.k, t.k), tslot(t.k, t.k), vdiag(t.k), smem, pipe(t)); break;
+        case TSQRT: K::tsqrt(tile(t.k, t.k), tile(t.i, t.k), tslot(t.i, t.k), smem, pipe(t)); break;
         case LARFB: K::template larfb<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem); break;
         default:
             K::template ssrfb<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend, smem);
@@ -980,6 +1046,17 @@ struct TrsmBody {
 // highest-priority ready task, runs it, and releases its successors; a
 // successor whose last dependency is released is pushed on its level's queue.
 // ===========================================================================
+// The successor a task releases when it starts rather than when it ends:
+// with the pipelined R_kk chain, TSQRT(i+1,k) after GEQRT(k) (i = k) or
+// TSQRT(i,k).  It is successor number 0 of those tasks; -1 when none.
+template <class G, class Body>
+__device__ __forceinline__ int64_t early_successor(const G &, const Body &, const Task &) { return -1; }
+template <int B, int IB>
+__device__ __forceinline__ int64_t early_successor(const FactorGraph &g, const FactorBody<B, IB> &b, const Task &t) {
+    if (!b.prog || (t.kind != GEQRT && t.kind != TSQRT) || t.i + 1 >= g.p) return -1;
+    return g.encode(TSQRT, t.i + 1, t.k, t.k, 0);
+}
+
 constexpr int kReadyCap = 64;  // ready successors collected per task before publishing
 
 template <class G, class Body>
@@ -1017,6 +1094,16 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         // for a continuation the thread that found it ready already did
         if (!cont) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const Task task = g.decode(t);
+        // a chain successor may start as soon as this task has started (it
+        // follows this task's progress inside its body)
+        const int64_t early = early_successor(g, body, task);
+        if (early >= 0 && tid == 0) {
+            if (__hip_atomic_fetch_add(&s.cnt[early], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) == 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                push_one(s, level_of(g, g.decode(early), o.policy), (int32_t)early);
+                wake_idle(s, 1, nworkers);
+            }
+        }
         const uint64_t t_acq = o.trace ? rt_clock() : 0;
         body.run(task, smem);
         const uint64_t t_body = o.trace ? rt_clock() : 0;
@@ -1035,7 +1122,7 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         }
         // Successors: the last predecessor to finish makes a task ready.
         const int ns = g.num_successors(task);
-        for (int n = tid; n < ns; n += NT) {
+        for (int n = tid + (early >= 0 ? 1 : 0); n < ns; n += NT) {
             const int64_t sidx = g.successor(task, n);
             const int32_t old = __hip_atomic_fetch_add(&s.cnt[sidx], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
             if (old == 1) {
@@ -1110,6 +1197,10 @@ __global__ void k_copy_status(const SchedState *st, int32_t *out, int only_error
 }
 
 __global__ void k_set_int(int32_t *out, int32_t v) { *out = v; }
+__global__ void k_fill_int(int32_t *out, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
 
 // Dense unit-lower copy of the reflectors of diagonal tile k (block k of the
 // grid): zeros above the diagonal, ones on it, V_kk below.
@@ -1178,8 +1269,10 @@ int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 int64_t wb_of(int64_t nrhs) { return cdiv(std::max<int64_t>(nrhs, 1), 16) * 16; }
 
 // Workspace: [tiles p*q*b*b][dense diagonal V q*b*b][B tiles p*b*wb][scheduler]
+// [R_kk chain progress words p*q int32]
 struct Sizes {
-    int64_t p, q, tiles_bytes, vd_bytes, btiles_bytes, sched_bytes, total;
+    int64_t p, q, tiles_bytes, vd_bytes, btiles_bytes, sched_bytes, prog_bytes, total;
+    int64_t prog_offset() const { return tiles_bytes + vd_bytes + btiles_bytes + sched_bytes; }
 };
 
 Sizes sizes_of(int64_t m, int64_t n, int64_t nrhs, int b) {
@@ -1195,7 +1288,8 @@ Sizes sizes_of(int64_t m, int64_t n, int64_t nrhs, int b) {
         nt = std::max(nt, TrsmGraph(z.q).num_tasks());
     }
     z.sched_bytes = align256(sched_bytes(nt));
-    z.total = z.tiles_bytes + z.vd_bytes + z.btiles_bytes + z.sched_bytes;
+    z.prog_bytes = align256(z.p * z.q * 4);
+    z.total = z.tiles_bytes + z.vd_bytes + z.btiles_bytes + z.sched_bytes + z.prog_bytes;
     return z;
 }
 
@@ -1320,6 +1414,23 @@ std::vector<int64_t> serial_order(const TrsmGraph &g) {
     return out;
 }
 
+// The factorisation body; with inner block 16 in persistent mode the R_kk
+// chain is pipelined (progress words cleared here, on the stream).
+template <int B, int IB>
+FactorBody<B, IB> factor_body(double *W, double *T, double *Vd, const Sizes &z, void *work, void *sched,
+                              const tqr_options *opt, hipStream_t stream) {
+    FactorBody<B, IB> body{W, T, Vd, (int)z.p};
+    const bool serial = opt && opt->mode == TQR_MODE_SERIAL;
+    if (IB == 16 && !serial) {
+        body.prog = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(work) + z.prog_offset());
+        body.status = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(sched) + offsetof(SchedState, status));
+        body.wait_ticks = (opt && opt->timeout_ticks > 0) ? opt->timeout_ticks : default_timeout_ticks();
+        const int64_t n = z.p * z.q;
+        hipLaunchKernelGGL(k_fill_int, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, body.prog, n, 0);
+    }
+    return body;
+}
+
 // ---- dispatch over the supported (b, ib) pairs ----------------------------
 template <int B, int IB>
 tqr_status factor_impl(int64_t m, int64_t n, double *A, int64_t lda, double *T, void *work, hipStream_t stream,
@@ -1331,7 +1442,7 @@ tqr_status factor_impl(int64_t m, int64_t n, double *A, int64_t lda, double *T, 
     hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, A, lda, m, n, W,
                        (int)z.p, B, B);
     FactorGraph g(z.p, z.q, B);
-    FactorBody<B, IB> body{W, T, Vd, (int)z.p};
+    const FactorBody<B, IB> body = factor_body<B, IB>(W, T, Vd, z, work, sched, opt, stream);
     tqr_status st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
     if (st != TQR_OK) return st;
     if (back_to_cm)
@@ -1559,8 +1670,8 @@ tqr_status tqr_solve_ls_ex(int64_t m, int64_t n, int64_t nrhs, double *A, int64_
         hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, A, lda, m, n, W,
                            (int)z.p, Bv, Bv);
         FactorGraph g(z.p, z.q, Bv);
-        tqr_status s1 = run_graph(g, FactorBody<Bv, Iv>{W, T, Vd, (int)z.p}, sched, TileKernels<Bv, Iv>::LDS_BYTES,
-                                  po, stream, po ? po->status : nullptr);
+        const FactorBody<Bv, Iv> body = factor_body<Bv, Iv>(W, T, Vd, z, work, sched, po, stream);
+        tqr_status s1 = run_graph(g, body, sched, TileKernels<Bv, Iv>::LDS_BYTES, po, stream, po ? po->status : nullptr);
         if (s1 != TQR_OK) return s1;
         hipLaunchKernelGGL(k_tiles_to_cm, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, W, (int)z.p, Bv,
                            Bv, A, lda, m, n);

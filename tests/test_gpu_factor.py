@@ -129,6 +129,12 @@ def test_schedules_are_bitwise_identical():
         assert np.array_equal(T, outs[0][1])
 
 
+def is_chain_edge(tu, tv):
+    """GEQRT(k) -> TSQRT(k+1,k) or TSQRT(i,k) -> TSQRT(i+1,k): the edges of
+    the chain that rewrites R_kk (task tuples are (kind, i, j, k, c))."""
+    return tu[0] in (0, 1) and tv[0] == 1 and tu[3] == tv[3] and tv[1] == tu[1] + 1
+
+
 def test_trace_respects_the_task_graph():
     torch = _torch()
     from paper_0707_3548_amd import tqr, workloads
@@ -143,9 +149,19 @@ def test_trace_respects_the_task_graph():
     start, end = tr[:, 0], tr[:, 3]
     assert np.all(end >= start) and np.all(start > 0)
     assert np.all(tr[:, 1] >= tr[:, 0]) and np.all(tr[:, 2] >= tr[:, 1]) and np.all(tr[:, 3] >= tr[:, 2])
+    overlapped = 0
     for u in range(nt):
+        tu = tqr.graph_task(p, q, b, u)
         for v in tqr.graph_successors(p, q, b, u):
-            assert start[v] >= end[u], (tqr.graph_task(p, q, b, u), tqr.graph_task(p, q, b, v))
+            tv = tqr.graph_task(p, q, b, v)
+            if is_chain_edge(tu, tv):
+                # the pipelined R_kk chain: TSQRT(i+1,k) may start once its
+                # predecessor has started and follows its progress inside
+                assert start[v] >= start[u], (tu, tv)
+                overlapped += int(start[v] < end[u])
+            else:
+                assert start[v] >= end[u], (tu, tv)
+    _say(f"chain tasks that overlapped their predecessor: {overlapped}")
 
 
 def test_timeout_path_reports_abort():
