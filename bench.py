@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--tile-b", type=int, default=256)
     ap.add_argument("--inner-ib", type=int, default=16)
-    ap.add_argument("--policy", choices=["paper", "lookahead"], default="paper")
+    ap.add_argument("--policy", choices=["paper", "lookahead", "column"], default="paper")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle's CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tall", action="store_true")
@@ -63,7 +63,7 @@ def time_factor(tqr, torch, A_host, b, ib, steps, warmup, policy):
     ws = tqr.Workspace(m, n, 0, b, ib)
     ev = tqr.HipEvents()
     evs = [(ev.create(), ev.create()) for _ in range(steps)]
-    pol = tqr.POLICY_LOOKAHEAD if policy == "lookahead" else tqr.POLICY_PAPER
+    pol = {"paper": tqr.POLICY_PAPER, "lookahead": tqr.POLICY_LOOKAHEAD, "column": tqr.POLICY_COLUMN}[policy]
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
     for w in range(warmup):
         tqr.factor(copies[w], b, ib, ws, policy=pol, status=status)

@@ -89,7 +89,7 @@ typedef struct tqr_options {
     int32_t struct_size;       /* sizeof(tqr_options) */
     int32_t workgroups;        /* persistent workers; 0 = one per resident slot */
     int32_t mode;              /* TQR_MODE_PERSISTENT or TQR_MODE_SERIAL */
-    int32_t policy;            /* TQR_POLICY_PAPER (default) or TQR_POLICY_LOOKAHEAD */
+    int32_t policy;            /* TQR_POLICY_PAPER (default), TQR_POLICY_LOOKAHEAD or TQR_POLICY_COLUMN */
     int64_t *trace;            /* device, 8 int64 per task or NULL: taken, acquired,
                                   body done, released (device constant-rate clock
                                   ticks), workgroup, XCD, the wave's
@@ -108,6 +108,8 @@ typedef struct tqr_options {
 #define TQR_MODE_SERIAL 1      /* one launch per task, in Algorithm 1 order (reference order) */
 #define TQR_POLICY_PAPER 0     /* ready tasks by kind: GEQRT > TSQRT > LARFB > SSRFB (Sec. 3.3) */
 #define TQR_POLICY_LOOKAHEAD 1 /* as PAPER, but updates of the next panel's tile column first */
+#define TQR_POLICY_COLUMN 2    /* as PAPER, with LARFB/SSRFB ordered by their tile column's distance
+                                  j - k from the panel (nearer first, six levels) */
 
 /* tqr_factor with explicit execution options (argument errors as
  * tqr_factor; -11 for a bad options struct). */

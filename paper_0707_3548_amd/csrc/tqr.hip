@@ -829,10 +829,18 @@ struct TileKernels {
     // per block.  For SSRFB the wave's top rows of the block are loaded first,
     // so that waiting for them does not wait for the prefetch.
     template <bool TRANS, bool TS>
+    // With pp.prev (forward order only) the reflectors are those of a TSQRT
+    // still running: block s is read once that task has published
+    // max(s, 1) (its panel s is then factored and stored).
     __device__ __forceinline__ static void apply_dbuf(Strip<B> &C, double *Top, const double *V, const double *T,
-                                                      int col0, bool owner, double *smem) {
+                                                      int col0, bool owner, double *smem, const Pipe &pp = Pipe{}) {
         double *buf[2] = {smem, smem + STAGE_DOUBLES};
+        const bool t0 = threadIdx.x == 0;
         StageRegs R;
+        if (TRANS && pp.prev) {
+            if (t0) pipe_wait(pp, 1);
+            __syncthreads();
+        }
         stage_fetch(V, T, (TRANS ? 0 : NB - 1) * IB, R);
         stage_commit(R, buf[0]);
         __syncthreads();
@@ -846,6 +854,7 @@ struct TileKernels {
             panel_update<B, IB, TRANS, TS>(C, TS ? Top + (size_t)col0 * B : nullptr, cur, LDV, cur + (size_t)LDV * IB,
                                            c0, owner, TS ? Wt : nullptr);
             if (si + 1 < NB) stage_commit(R, buf[(si + 1) & 1]);
+            if (TRANS && pp.prev && t0 && si + 2 < NB) pipe_wait(pp, si + 2);
             __syncthreads();
         }
     }
@@ -883,7 +892,7 @@ struct TileKernels {
     // reflectors (V_ik, T_ik) of a TSQRT tile.
     template <bool TRANS>
     __device__ __forceinline__ static void ssrfb(double *Top, double *Cb, const double *Vik, const double *Tik, int cbeg, int cend,
-                                 double *smem) {
+                                 double *smem, const Pipe &pp = Pipe{}) {
         double *Vl = smem, *Tl = smem + (size_t)LDV * IB;
         const int want = cbeg + 16 * wave_id();
         const int col0 = min(want, cend - 16);
@@ -891,7 +900,7 @@ struct TileKernels {
         Strip<B> C;
         strip_load<B>(C, Cb + (size_t)col0 * B, B);
         if constexpr (DBUF) {
-            apply_dbuf<TRANS, true>(C, Top, Vik, Tik, col0, owner, smem);
+            apply_dbuf<TRANS, true>(C, Top, Vik, Tik, col0, owner, smem, pp);
         } else {
 #pragma unroll 1
             for (int si = 0; si < NB; ++si) {
@@ -926,8 +935,15 @@ struct FactorBody {
     __device__ Pipe pipe(const Task &t) const {
         Pipe pp{nullptr, nullptr, status, 0};
         if (prog) {
-            if (t.kind == TSQRT) pp.prev = prog + (int64_t)t.k * p + t.i - 1;
-            if (t.i + 1 < p) pp.mine = prog + (int64_t)t.k * p + t.i;
+            const int64_t row = (int64_t)t.k * p;
+            if (t.kind == TSQRT) {
+                pp.prev = prog + row + t.i - 1;
+                pp.mine = prog + row + t.i;  // read by TSQRT(i+1,k) and SSRFB(i,k+1,k)
+            } else if (t.kind == GEQRT) {
+                if (t.i + 1 < p) pp.mine = prog + row + t.i;
+            } else if (t.kind == SSRFB && t.j == t.k + 1) {
+                pp.prev = prog + row + t.i;  // the TSQRT(i,k) whose reflectors it applies
+            }
             pp.deadline = rt_clock() + (uint64_t)wait_ticks;
         }
         return pp;
@@ -941,7 +957,8 @@ struct FactorBody {
         case TSQRT: K::tsqrt(tile(t.k, t.k), tile(t.i, t.k), tslot(t.i, t.k), smem, pipe(t)); break;
         case LARFB: K::template larfb<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem); break;
         default:
-            K::template ssrfb<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend, smem);
+            K::template ssrfb<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend, smem,
+                                    pipe(t));
             break;
         }
     }
@@ -1046,15 +1063,19 @@ struct TrsmBody {
 // highest-priority ready task, runs it, and releases its successors; a
 // successor whose last dependency is released is pushed on its level's queue.
 // ===========================================================================
-// The successor a task releases when it starts rather than when it ends:
-// with the pipelined R_kk chain, TSQRT(i+1,k) after GEQRT(k) (i = k) or
-// TSQRT(i,k).  It is successor number 0 of those tasks; -1 when none.
+// Successors a task releases when it starts rather than when it ends (they
+// follow its progress word inside their bodies): with the pipelined chain,
+// TSQRT(i+1,k) after GEQRT(k) (i = k) or TSQRT(i,k), and the strips of
+// SSRFB(i,k+1,k) after TSQRT(i,k).  They are the first successors in the
+// graph's order; returns how many.
 template <class G, class Body>
-__device__ __forceinline__ int64_t early_successor(const G &, const Body &, const Task &) { return -1; }
+__device__ __forceinline__ int early_successors(const G &, const Body &, const Task &) { return 0; }
 template <int B, int IB>
-__device__ __forceinline__ int64_t early_successor(const FactorGraph &g, const FactorBody<B, IB> &b, const Task &t) {
-    if (!b.prog || (t.kind != GEQRT && t.kind != TSQRT) || t.i + 1 >= g.p) return -1;
-    return g.encode(TSQRT, t.i + 1, t.k, t.k, 0);
+__device__ __forceinline__ int early_successors(const FactorGraph &g, const FactorBody<B, IB> &b, const Task &t) {
+    if (!b.prog || (t.kind != GEQRT && t.kind != TSQRT)) return 0;
+    const int chain = t.i + 1 < g.p ? 1 : 0;
+    if (t.kind == GEQRT) return chain;
+    return chain + (t.k + 1 < g.q ? (int)g.S : 0);
 }
 
 constexpr int kReadyCap = 64;  // ready successors collected per task before publishing
@@ -1094,15 +1115,20 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         // for a continuation the thread that found it ready already did
         if (!cont) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const Task task = g.decode(t);
-        // a chain successor may start as soon as this task has started (it
-        // follows this task's progress inside its body)
-        const int64_t early = early_successor(g, body, task);
-        if (early >= 0 && tid == 0) {
-            if (__hip_atomic_fetch_add(&s.cnt[early], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) == 1) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-                push_one(s, level_of(g, g.decode(early), o.policy), (int32_t)early);
-                wake_idle(s, 1, nworkers);
+        // successors that follow this task's progress may start as soon as
+        // it has started
+        const int nearly = early_successors(g, body, task);
+        if (nearly > 0 && tid == 0) {
+            int pushed = 0;
+            for (int n = 0; n < nearly; ++n) {
+                const int64_t e = g.successor(task, n);
+                if (__hip_atomic_fetch_add(&s.cnt[e], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) == 1) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                    push_one(s, level_of(g, g.decode(e), o.policy), (int32_t)e);
+                    ++pushed;
+                }
             }
+            if (pushed > 0) wake_idle(s, pushed, nworkers);
         }
         const uint64_t t_acq = o.trace ? rt_clock() : 0;
         body.run(task, smem);
@@ -1122,7 +1148,7 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         }
         // Successors: the last predecessor to finish makes a task ready.
         const int ns = g.num_successors(task);
-        for (int n = tid + (early >= 0 ? 1 : 0); n < ns; n += NT) {
+        for (int n = tid + nearly; n < ns; n += NT) {
             const int64_t sidx = g.successor(task, n);
             const int32_t old = __hip_atomic_fetch_add(&s.cnt[sidx], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
             if (old == 1) {
@@ -1502,7 +1528,8 @@ tqr_status check_opts(const tqr_options *o) {
     if (!o) return TQR_OK;
     if (o->struct_size != (int32_t)sizeof(tqr_options)) return -11;
     if (o->mode != TQR_MODE_PERSISTENT && o->mode != TQR_MODE_SERIAL) return -11;
-    if (o->policy != TQR_POLICY_PAPER && o->policy != TQR_POLICY_LOOKAHEAD) return -11;
+    if (o->policy != TQR_POLICY_PAPER && o->policy != TQR_POLICY_LOOKAHEAD && o->policy != TQR_POLICY_COLUMN)
+        return -11;
     if (o->workgroups < 0) return -11;
     return TQR_OK;
 }

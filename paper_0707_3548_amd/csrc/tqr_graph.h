@@ -42,7 +42,7 @@ namespace tqr {
 
 enum Kind : int { GEQRT = 0, TSQRT = 1, LARFB = 2, SSRFB = 3 };
 constexpr int kStripCols = 64;   // columns of one update strip (one workgroup)
-constexpr int kLevels = 5;       // ready-queue priority levels
+constexpr int kLevels = 8;       // ready-queue priority levels
 
 struct Task {
     int kind, i, j, k, c;
@@ -153,14 +153,19 @@ struct FactorGraph {
         }
     }
 
-    // priority level: 0 is served first
+    // priority level: 0 is served first.  Policy 0 (the paper's): by kind;
+    // 1: the updates of tile column k+1 (the next panel) before the other
+    // updates; 2: updates by the distance j-k of their tile column from the
+    // panel, levels 2..7 (the last holds every column from k+6 on).
     TQR_HD int level(const Task &t, int policy) const {
-        switch (t.kind) {
-        case GEQRT: return 0;
-        case TSQRT: return 1;
-        case LARFB: return (policy == 1 && t.j == t.k + 1) ? 2 : 3;
-        default: return (policy == 1 && t.j == t.k + 1) ? 2 : 4;
+        if (t.kind == GEQRT) return 0;
+        if (t.kind == TSQRT) return 1;
+        if (policy == 2) {
+            const int d = t.j - t.k - 1;
+            return 2 + (d < 5 ? d : 5);
         }
+        if (t.kind == LARFB) return (policy == 1 && t.j == t.k + 1) ? 2 : 3;
+        return (policy == 1 && t.j == t.k + 1) ? 2 : 4;
     }
 };
 

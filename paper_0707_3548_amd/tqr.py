@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtqr.so")
 
 MODE_PERSISTENT, MODE_SERIAL = 0, 1
-POLICY_PAPER, POLICY_LOOKAHEAD = 0, 1
+POLICY_PAPER, POLICY_LOOKAHEAD, POLICY_COLUMN = 0, 1, 2
 TQR_EDEVICE, TQR_EABORTED = -1000, -1001
 
 

@@ -120,7 +120,7 @@ def test_schedules_are_bitwise_identical():
     A = workloads.gaussian(640, 448, seed=5)
     outs = []
     for kw in [dict(mode=tqr.MODE_SERIAL), dict(workgroups=1), dict(workgroups=7), dict(),
-               dict(policy=tqr.POLICY_LOOKAHEAD)]:
+               dict(policy=tqr.POLICY_LOOKAHEAD), dict(policy=tqr.POLICY_COLUMN)]:
         _say(f"case schedule {kw}")
         dA, ws = run_factor(A, 64, 16, **kw)
         outs.append((dA.cpu().numpy(), ws.T.cpu().numpy()))
@@ -130,9 +130,13 @@ def test_schedules_are_bitwise_identical():
 
 
 def is_chain_edge(tu, tv):
-    """GEQRT(k) -> TSQRT(k+1,k) or TSQRT(i,k) -> TSQRT(i+1,k): the edges of
-    the chain that rewrites R_kk (task tuples are (kind, i, j, k, c))."""
-    return tu[0] in (0, 1) and tv[0] == 1 and tu[3] == tv[3] and tv[1] == tu[1] + 1
+    """Edges whose successor follows its predecessor's progress (task tuples
+    are (kind, i, j, k, c)): GEQRT(k) -> TSQRT(k+1,k) and TSQRT(i,k) ->
+    TSQRT(i+1,k) on the chain that rewrites R_kk, and TSQRT(i,k) ->
+    SSRFB(i,k+1,k) (the next column's update)."""
+    if tu[0] in (0, 1) and tv[0] == 1 and tu[3] == tv[3] and tv[1] == tu[1] + 1:
+        return True
+    return tu[0] == 1 and tv[0] == 3 and tv[1] == tu[1] and tv[3] == tu[3] and tv[2] == tu[3] + 1
 
 
 def test_trace_respects_the_task_graph():
