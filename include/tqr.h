@@ -172,6 +172,40 @@ tqr_status tqr_solve_ls_ex(int64_t m, int64_t n, int64_t nrhs, double *A, int64_
                            int tile_b, int inner_ib, double *T, void *work, int64_t work_bytes,
                            int32_t *d_info, hipStream_t stream, const tqr_options *options);
 
+/* ---- Batched factorisation: many independent problems in one launch ----
+ * Each problem is factorised exactly as tqr_factor does it (the tiled
+ * algorithm of Sec. 3.1, Algorithm 1, inner block 16), with its own tile
+ * size.  One persistent launch; a workgroup takes the next problem from a
+ * counter, converts it to tiles, runs its tasks in the order of Algorithm 1
+ * and converts it back, so problems are independent of the schedule and of
+ * each other (bitwise).  Problems are taken in array order: put the largest
+ * first. */
+typedef struct tqr_batch_problem {
+    int64_t m, n, lda;   /* m >= n >= 0, lda >= max(1, m) */
+    double *A;           /* device, column-major; overwritten as by tqr_factor */
+    double *T;           /* device, tqr_t_elems(m, n, tile_b, 16) doubles, written */
+    int32_t tile_b;      /* 16, 32 or 64 */
+    int32_t reserved;    /* 0 */
+    int64_t work_offset; /* byte offset of the problem's tiles in work: set by tqr_batch_plan */
+} tqr_batch_problem;
+
+/* Host-side plan: checks every problem and sets its work_offset.  Returns
+ * the workspace bytes that tqr_factor_batched needs, or -1 (count < 0),
+ * -2 (problems null, or a problem with m < n, n < 0, lda < max(1, m), a
+ * null A or T with m*n > 0, or an unsupported tile_b: the message names the
+ * index). */
+int64_t tqr_batch_plan(int64_t count, tqr_batch_problem *problems);
+
+/* Factorises the planned problems.  d_problems: device copy of the planned
+ * array (count entries); work: tqr_batch_plan's bytes; d_status (optional
+ * device int): 0, or i+1 when problem i had an unsupported tile_b (it is
+ * skipped).  workgroups: 0 for one per resident slot, else at most that
+ * many.  Enqueued on stream; no host synchronisation, no memset (the launch
+ * may be captured in a graph).  Errors: -1 count, -2 d_problems null,
+ * -3 work null, -4 work_bytes below 256, -7 workgroups < 0. */
+tqr_status tqr_factor_batched(int64_t count, const tqr_batch_problem *d_problems, void *work, int64_t work_bytes,
+                              int32_t *d_status, int32_t workgroups, hipStream_t stream);
+
 /* Description of the last error returned to the calling host thread. */
 const char *tqr_last_error_string(void);
 

@@ -45,6 +45,19 @@ class Options(ctypes.Structure):
     ]
 
 
+class BatchProblem(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("lda", ctypes.c_int64),
+        ("A", ctypes.c_void_p),
+        ("T", ctypes.c_void_p),
+        ("tile_b", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("work_offset", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 
@@ -72,6 +85,10 @@ def lib() -> ctypes.CDLL:
         L.tqr_solve_ls.restype = i32
         L.tqr_solve_ls_ex.argtypes = [i64, i64, i64, dp, i64, dp, i64, i32, i32, dp, vp, i64, vp, vp, ctypes.POINTER(Options)]
         L.tqr_solve_ls_ex.restype = i32
+        L.tqr_batch_plan.argtypes = [i64, ctypes.POINTER(BatchProblem)]
+        L.tqr_batch_plan.restype = i64
+        L.tqr_factor_batched.argtypes = [i64, vp, vp, i64, vp, ctypes.c_int32, vp]
+        L.tqr_factor_batched.restype = i32
         L.tqr_last_error_string.argtypes = []
         L.tqr_last_error_string.restype = ctypes.c_char_p
         L.tqr_graph_tasks.argtypes = [i64, i64, i32]
@@ -209,6 +226,71 @@ def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None, *, workgroups:
                                 ws.T.data_ptr(), ws.work.data_ptr(), ws.work.numel(), info.data_ptr(), _stream())
         _check("tqr_solve_ls", rc)
     return B, info
+
+
+# ---- batched factorisation ------------------------------------------------------
+
+class Batch:
+    """Many independent problems factorised in one launch (tqr_factor_batched).
+
+    ``shapes`` is a list of (m, n) with m >= n; ``tile_bs`` the tile size of
+    each problem (16, 32 or 64; see autotune.tile_for).  The matrices live
+    column-major, back to back, in one device buffer ``A``; ``matrix(i)`` is
+    problem i's view.  Problems are launched largest first (by the standard
+    flop count), which the result does not depend on."""
+
+    def __init__(self, shapes, tile_bs, device="cuda"):
+        self.shapes = [(int(m), int(n)) for m, n in shapes]
+        self.tile_bs = [int(b) for b in tile_bs]
+        if len(self.tile_bs) != len(self.shapes):
+            raise ValueError("one tile size per problem")
+        count = len(self.shapes)
+        a_off, t_off, a, t = [], [], 0, 0
+        for (m, n), b in zip(self.shapes, self.tile_bs):
+            a_off.append(a)
+            t_off.append(t)
+            a += m * n
+            t += max(t_elems(m, n, b, 16), 0)
+        self.A = torch.zeros(max(a, 1), dtype=torch.float64, device=device)
+        self.T = torch.zeros(max(t, 1), dtype=torch.float64, device=device)
+        self.a_off, self.t_off = a_off, t_off
+        order = sorted(range(count), key=lambda i: -(self.shapes[i][1] ** 2 * (self.shapes[i][0] - self.shapes[i][1] / 3.0)))
+        probs = (BatchProblem * max(count, 1))()
+        base_a, base_t = self.A.data_ptr(), self.T.data_ptr()
+        for slot, i in enumerate(order):
+            m, n = self.shapes[i]
+            probs[slot] = BatchProblem(m, n, max(1, m), base_a + 8 * a_off[i], base_t + 8 * t_off[i], self.tile_bs[i], 0, 0)
+        nb = int(lib().tqr_batch_plan(count, probs))
+        if nb < 0:
+            _check("tqr_batch_plan", nb)
+        self.work = torch.empty(nb, dtype=torch.uint8, device=device)
+        raw = bytes(ctypes.string_at(ctypes.addressof(probs), ctypes.sizeof(BatchProblem) * count))
+        self.desc = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device) if count else torch.empty(
+            0, dtype=torch.uint8, device=device)
+        self.count = count
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def load(self, mats) -> None:
+        """Copies host matrices (one per problem, shapes as given) in."""
+        import numpy as np
+        flat = np.concatenate([np.asarray(M, dtype=np.float64).ravel(order="F") for M in mats]) if mats else np.zeros(0)
+        if flat.size:
+            self.A[:flat.size].copy_(torch.from_numpy(flat))
+
+    def matrix(self, i: int) -> torch.Tensor:
+        """Problem i as an (m, n) column-major view of the shared buffer."""
+        m, n = self.shapes[i]
+        return self.A[self.a_off[i]:self.a_off[i] + m * n].view(n, m).t()
+
+    def t_slots(self, i: int) -> torch.Tensor:
+        m, n = self.shapes[i]
+        return self.T[self.t_off[i]:self.t_off[i] + t_elems(m, n, self.tile_bs[i], 16)]
+
+    def factor(self, workgroups: int = 0) -> None:
+        rc = lib().tqr_factor_batched(self.count, ctypes.c_void_p(self.desc.data_ptr() if self.count else 0),
+                                      ctypes.c_void_p(self.work.data_ptr()), self.work.numel(),
+                                      ctypes.c_void_p(self.status.data_ptr()), int(workgroups), _stream())
+        _check("tqr_factor_batched", rc)
 
 
 # ---- task-graph introspection (host only) ------------------------------------

@@ -124,3 +124,12 @@ def ls_request(m: int, n: int, nrhs: int, cond: float, seed: int, noise: float =
     x = gx.standard_normal((n, nrhs))
     b = np.asfortranarray(A @ x + noise * gn.standard_normal((m, nrhs)))
     return A, b, x
+
+
+def fill_normal_device(t, seed: int) -> None:
+    """Fills a device tensor in place with N(0, 1) numbers from torch's
+    seeded device generator (for batches too large to draw on the host)."""
+    import torch
+    g = torch.Generator(device=t.device)
+    g.manual_seed(seed)
+    t.normal_(generator=g)

@@ -1,0 +1,141 @@
+"""Batched factorisation (many independent problems in one launch).
+
+GPU: every problem's factor (R, the tiled V and T) is bitwise the one the
+single-problem path computes with the same tiling (both apply the same
+operations to every tile in the same order), R matches the unblocked oracle
+after sign normalisation, and a launch captured in a graph gives the eager
+result on every replay.  CPU: the host plan's checks and offsets, and the
+tile-size table / autotuner on a fake timer."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0707_3548_amd import autotune, tqr, workloads
+
+
+def _plan(shapes, tiles, null_a=False):
+    probs = (tqr.BatchProblem * max(len(shapes), 1))()
+    for i, ((m, n), b) in enumerate(zip(shapes, tiles)):
+        probs[i] = tqr.BatchProblem(m, n, max(1, m), 0 if null_a else 4096, 8192, b, 0, 0)
+    return tqr.lib().tqr_batch_plan(len(shapes), probs), probs
+
+
+def test_plan_offsets_and_checks():
+    nb, probs = _plan([(40, 17), (16, 16), (300, 2)], [16, 32, 64])
+    assert nb > 256
+    offs = [probs[i].work_offset for i in range(3)]
+    assert offs[0] == 256 and all(o % 256 == 0 for o in offs) and offs == sorted(offs)
+    # tiles + dense V copies of problem 0: p=3, q=2 tiles of 16x16 plus q diagonal blocks
+    assert offs[1] - offs[0] == -(-((3 * 2 + 2) * 256 * 8) // 256) * 256
+    assert _plan([(10, 20)], [16])[0] == -2          # m < n
+    assert _plan([(40, 17)], [48])[0] == -2          # tile size
+    assert _plan([(40, 17)], [16], null_a=True)[0] == -2
+    assert b"problem 0" in tqr.lib().tqr_last_error_string()
+    assert tqr.lib().tqr_batch_plan(-1, None) == -1
+    assert tqr.lib().tqr_batch_plan(0, None) == 256
+
+
+def test_factor_batched_argument_checks():
+    L = tqr.lib()
+    assert L.tqr_factor_batched(-1, None, None, 0, None, 0, None) == -1
+    assert L.tqr_factor_batched(3, None, ctypes.c_void_p(64), 4096, None, 0, None) == -2
+    assert L.tqr_factor_batched(3, ctypes.c_void_p(64), None, 4096, None, 0, None) == -3
+    assert L.tqr_factor_batched(3, ctypes.c_void_p(64), ctypes.c_void_p(64), 100, None, 0, None) == -4
+    assert L.tqr_factor_batched(3, ctypes.c_void_p(64), ctypes.c_void_p(64), 4096, None, -1, None) == -7
+
+
+def test_tile_table_and_tuner():
+    assert autotune.tile_for(8) == 16 and autotune.tile_for(40) == 32 and autotune.tile_for(500) == 64
+    # a fake device where tile 32 is fastest below n = 64 and tile 64 above
+    def sample(lo, hi):
+        return [(max(16, lo + 1), lo + 1)] if lo < 512 else []
+
+    def time_batch(shapes, b):
+        n = shapes[0][1]
+        return {16: 3.0, 32: 1.0, 64: 2.0}[b] if n < 64 else {16: 5.0, 32: 4.0, 64: 1.0}[b]
+
+    table = autotune.tune(sample, time_batch)
+    assert table == [(0, 32), (64, 64)]
+    assert autotune.tile_for(10, table) == 32 and autotune.tile_for(100, table) == 64
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+EDGE = [(16, 16), (16, 8), (17, 1), (64, 64), (65, 64), (100, 33), (512, 512), (300, 299), (40, 40), (33, 32)]
+
+
+@pytest.mark.gpu
+def test_batched_matches_single_problem_path():
+    torch = _torch()
+    shapes = workloads.batch_shapes(48, seed=5) + EDGE
+    tiles = [autotune.tile_for(n) for _, n in shapes]
+    tiles[-3:] = [16, 32, 64]
+    print(f"case batched vs single: {len(shapes)} problems", flush=True)
+    mats = workloads.batch_matrices(shapes, seed=6)
+    bt = tqr.Batch(shapes, tiles)
+    bt.load(mats)
+    bt.factor()
+    torch.cuda.synchronize()
+    assert int(bt.status.item()) == 0
+    for i, ((m, n), b) in enumerate(zip(shapes, tiles)):
+        dA = tqr.fortran(torch.from_numpy(mats[i]).cuda())
+        ws = tqr.Workspace(m, n, 0, b, 16)
+        tqr.factor(dA, b, 16, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(bt.matrix(i), dA), f"problem {i} ({m}x{n}, b={b}): factor differs"
+        assert torch.equal(bt.t_slots(i), ws.T[:bt.t_slots(i).numel()]), f"problem {i}: T differs"
+
+
+@pytest.mark.gpu
+def test_batched_r_matches_oracle():
+    torch = _torch()
+    shapes = workloads.batch_shapes(200, seed=7)
+    tiles = [autotune.tile_for(n) for _, n in shapes]
+    print(f"case batched vs oracle: {len(shapes)} problems", flush=True)
+    mats = workloads.batch_matrices(shapes, seed=8)
+    bt = tqr.Batch(shapes, tiles)
+    bt.load(mats)
+    bt.factor()
+    torch.cuda.synchronize()
+    for i in range(0, len(shapes), 7):
+        m, n = shapes[i]
+        R = np.triu(bt.matrix(i).cpu().numpy()[:n, :])
+        _, R_or = oracle.qr(mats[i])
+        assert oracle.rel_fro(oracle.sign_normalize(R), R_or) < 1e-10, (i, m, n)
+
+
+@pytest.mark.gpu
+def test_batched_graph_replays_match_eager():
+    torch = _torch()
+    shapes = workloads.batch_shapes(300, seed=9)
+    tiles = [autotune.tile_for(n) for _, n in shapes]
+    print("case batched graph replay: 300 problems", flush=True)
+    mats = workloads.batch_matrices(shapes, seed=10)
+    bt = tqr.Batch(shapes, tiles)
+    bt.load(mats)
+    pristine = bt.A.clone()
+    bt.factor()
+    torch.cuda.synchronize()
+    eager_A, eager_T = bt.A.clone(), bt.T.clone()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    bt.A.copy_(pristine)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        bt.factor()
+    for rep in range(3):
+        bt.A.copy_(pristine)
+        bt.T.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(bt.A, eager_A), f"replay {rep}: A differs"
+        assert torch.equal(bt.T, eager_T), f"replay {rep}: T differs"
+        assert int(bt.status.item()) == 0
