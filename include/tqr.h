@@ -102,6 +102,8 @@ typedef struct tqr_options {
     int64_t timeout_ticks;     /* per-wait bound in device clock ticks; 0 = 2 s */
     void *event_begin;         /* hipEvent_t recorded on `stream` right before the  */
     void *event_end;           /* scheduler launch and right after it, or NULL     */
+    int32_t precision;         /* TQR_PRECISION_FP64 (0, default) or TQR_PRECISION_FP32_UPDATES */
+    int32_t reserved;          /* 0 */
 } tqr_options;
 
 #define TQR_MODE_PERSISTENT 0  /* one launch; tasks run out of order as the graph allows */
@@ -110,6 +112,12 @@ typedef struct tqr_options {
 #define TQR_POLICY_LOOKAHEAD 1 /* as PAPER, but updates of the next panel's tile column first */
 #define TQR_POLICY_COLUMN 2    /* as PAPER, with LARFB/SSRFB ordered by their tile column's distance
                                   j - k from the panel (nearer first, six levels) */
+#define TQR_PRECISION_FP64 0         /* every kernel in FP64 */
+#define TQR_PRECISION_FP32_UPDATES 1 /* LARFB and SSRFB (the trailing updates, nearly all the
+                                        flops) on the FP32 matrix cores; GEQRT/TSQRT (norms,
+                                        reflectors, T) in FP64; inner_ib must be 16.  The
+                                        factor is then accurate to FP32 rounding: a starting
+                                        point for FP64 refinement (tqr_solve_ls_mixed). */
 
 /* tqr_factor with explicit execution options (argument errors as
  * tqr_factor; -11 for a bad options struct). */
@@ -171,6 +179,29 @@ tqr_status tqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t l
 tqr_status tqr_solve_ls_ex(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb,
                            int tile_b, int inner_ib, double *T, void *work, int64_t work_bytes,
                            int32_t *d_info, hipStream_t stream, const tqr_options *options);
+
+/* ---- Mixed-precision least squares with FP64 refinement ----
+ * min ||A X - B||_F for m >= n.  A copy of A is factorised with the trailing
+ * updates on the FP32 matrix cores (TQR_PRECISION_FP32_UPDATES; options may
+ * ask for TQR_PRECISION_FP64 instead), then `iterations` steps of iterative
+ * refinement of the augmented system [I A; A^T 0][r; x] = [B; 0] (Bjorck)
+ * run with FP64 residuals: f = B - r - A x, g = -A^T r (FP64 kernels on the
+ * caller's A), the correction from the factor (h = R^{-T} g,
+ * d = Q^T f, dx = R^{-1}(d[0:n] - h), dr = Q [h; d[n:m]]), x += dx, r += dr,
+ * starting from x = 0, r = B.  Each step reduces the error by about
+ * cond(A) times the factor's relative accuracy.  A and B are not modified.
+ *   X      : device, n x nrhs column-major (ldx >= max(1, n)), written.
+ *   T      : device, tqr_t_elems(m, n, tile_b, 16) doubles, written.
+ *   work   : tqr_ls_mixed_workspace_bytes(m, n, nrhs, tile_b) bytes.
+ *   d_info : device int: 0, or k > 0 when R(k,k) is exactly zero.
+ * inner_ib is 16.  Errors: -1 m, -2 n, -3 nrhs, -4 A null, -5 lda, -6 B null,
+ * -7 ldb, -8 X null, -9 ldx, -10 tile_b (64, 128 or 256), -11 iterations
+ * (0..50), -12 T null, -13 work null, -14 work_bytes, -15 d_info null,
+ * -16 options. */
+int64_t tqr_ls_mixed_workspace_bytes(int64_t m, int64_t n, int64_t nrhs, int tile_b);
+tqr_status tqr_solve_ls_mixed(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+                              int64_t ldb, double *X, int64_t ldx, int tile_b, int iterations, double *T, void *work,
+                              int64_t work_bytes, int32_t *d_info, hipStream_t stream, const tqr_options *options);
 
 /* ---- Batched factorisation: many independent problems in one launch ----
  * Each problem is factorised exactly as tqr_factor does it (the tiled

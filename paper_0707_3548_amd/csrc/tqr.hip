@@ -913,12 +913,83 @@ struct TileKernels {
         }
         if (owner) strip_store<B>(C, Cb + (size_t)col0 * B, B);
     }
+
+    // ---- FP32 precision tier of LARFB / SSRFB (inner block 16) -----------
+    // V and T of a block are fetched as FP64 and written to LDS as floats;
+    // the strip is converted to float once when loaded and back when stored.
+    __device__ __forceinline__ static void stage_commit_f(const StageRegs &R, float *buf) {
+        const int tid = threadIdx.x;
+        float *Vl = buf, *Tl = buf + (size_t)LDV * IB;
+#pragma unroll
+        for (int k = 0; k < STAGE_V; ++k) {
+            const int idx = tid + k * NT, r = idx % B, c = idx / B;
+            Vl[c * LDV + r] = (float)R.v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < STAGE_T; ++k) {
+            const int idx = tid + k * NT;
+            if (idx < IB * IB) Tl[idx] = (float)R.t[k];
+        }
+    }
+
+    template <bool TRANS, bool TS>
+    __device__ __forceinline__ static void apply_dbuf_f32(StripF<B> &C, double *Top, const double *V, const double *T,
+                                                          int col0, bool owner, double *smem, const Pipe &pp = Pipe{}) {
+        static_assert(IB == 16, "the FP32 tier works with inner block 16");
+        constexpr size_t STAGE_F = (size_t)LDV * IB + IB * IB;
+        float *fb = reinterpret_cast<float *>(smem);
+        float *buf[2] = {fb, fb + STAGE_F};
+        const bool t0 = threadIdx.x == 0;
+        StageRegs R;
+        if (TRANS && pp.prev) {
+            if (t0) pipe_wait(pp, 1);
+            __syncthreads();
+        }
+        stage_fetch(V, T, (TRANS ? 0 : NB - 1) * IB, R);
+        stage_commit_f(R, buf[0]);
+        __syncthreads();
+#pragma unroll 1
+        for (int si = 0; si < NB; ++si) {
+            const int c0 = (TRANS ? si : NB - 1 - si) * IB;
+            float *cur = buf[si & 1];
+            if (si + 1 < NB) stage_fetch(V, T, (TRANS ? si + 1 : NB - 2 - si) * IB, R);
+            panel_update_f32<B, TRANS, TS>(C, TS ? Top + (size_t)col0 * B : nullptr, cur, LDV, cur + (size_t)LDV * IB,
+                                           c0, owner);
+            if (si + 1 < NB) stage_commit_f(R, buf[(si + 1) & 1]);
+            if (TRANS && pp.prev && t0 && si + 2 < NB) pipe_wait(pp, si + 2);
+            __syncthreads();
+        }
+    }
+
+    template <bool TRANS>
+    __device__ __forceinline__ static void larfb_f32(const double *Vd, const double *Tkk, double *Cb, int cbeg, int cend,
+                                                     double *smem) {
+        const int want = cbeg + 16 * wave_id();
+        const int col0 = min(want, cend - 16);
+        const bool owner = want < cend;
+        StripF<B> C;
+        strip_load_f<B>(C, Cb + (size_t)col0 * B, B);
+        apply_dbuf_f32<TRANS, false>(C, nullptr, Vd, Tkk, col0, owner, smem);
+        if (owner) strip_store_f<B>(C, Cb + (size_t)col0 * B, B);
+    }
+
+    template <bool TRANS>
+    __device__ __forceinline__ static void ssrfb_f32(double *Top, double *Cb, const double *Vik, const double *Tik, int cbeg,
+                                                     int cend, double *smem, const Pipe &pp = Pipe{}) {
+        const int want = cbeg + 16 * wave_id();
+        const int col0 = min(want, cend - 16);
+        const bool owner = want < cend;
+        StripF<B> C;
+        strip_load_f<B>(C, Cb + (size_t)col0 * B, B);
+        apply_dbuf_f32<TRANS, true>(C, Top, Vik, Tik, col0, owner, smem, pp);
+        if (owner) strip_store_f<B>(C, Cb + (size_t)col0 * B, B);
+    }
 };
 
 // ---------------------------------------------------------------------------
 // Task bodies
 // ---------------------------------------------------------------------------
-template <int B, int IB>
+template <int B, int IB, bool F32 = false>
 struct FactorBody {
     using K = TileKernels<B, IB>;
     double *W;   // tiles
@@ -955,10 +1026,19 @@ struct FactorBody {
         switch (t.kind) {
         case GEQRT: K::geqrt(tile(t.k, t.k), tslot(t.k, t.k), vdiag(t.k), smem, pipe(t)); break;
         case TSQRT: K::tsqrt(tile(t.k, t.k), tile(t.i, t.k), tslot(t.i, t.k), smem, pipe(t)); break;
-        case LARFB: K::template larfb<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem); break;
+        case LARFB:
+            if constexpr (F32)
+                K::template larfb_f32<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem);
+            else
+                K::template larfb<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem);
+            break;
         default:
-            K::template ssrfb<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend, smem,
-                                    pipe(t));
+            if constexpr (F32)
+                K::template ssrfb_f32<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend,
+                                            smem, pipe(t));
+            else
+                K::template ssrfb<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend, smem,
+                                        pipe(t));
             break;
         }
     }
@@ -1058,6 +1138,78 @@ struct TrsmBody {
     }
 };
 
+// Forward substitution with R^T on the tiles of B (refinement of least
+// squares): G'(i,j): Y_i -= R_ji^T X_j;  D'(i): solve R_ii^T X_i = Y_i.
+template <int B>
+struct TrsmTBody {
+    const double *W;
+    double *Bt;
+    int p, wb;
+    int64_t nrow;
+    __device__ const double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
+    __device__ double *btile(int i) const { return Bt + (int64_t)i * B * wb; }
+    __device__ __forceinline__ void run(const Task &t, double *smem) const {
+        if (t.kind == 1) {
+            // A operand of k-slice (kb, s): R_ji^T[16rb + l%16][16kb + 4s + l/16]
+            //                              = R_ji[16kb + 4s + l/16][16rb + l%16]
+            const double *R = tile(t.j, t.i);
+            const double *X = btile(t.j);
+            double *Y = btile(t.i);
+            const int l = lane_id();
+            for (int col0 = 16 * wave_id(); col0 < wb; col0 += 16 * NWAVES) {
+                Strip<B> C;
+                strip_load<B>(C, Y + (size_t)col0 * B, B);
+                const double *xp = X + (size_t)(col0 + (l & 15)) * B + (l >> 4);
+                const double *rp = R + (size_t)(l & 15) * B + (l >> 4);
+#pragma unroll 1
+                for (int kb = 0; kb < B / 16; ++kb) {
+                    const d4 x = -ld4s(xp + 16 * kb, 4);
+                    const double *rk = rp + 16 * kb;
+#pragma unroll
+                    for (int rb = 0; rb < B / 16; ++rb) {
+                        const double *q = rk + (size_t)16 * rb * B;
+                        C.v[rb] = mfma(q[0], x.x, C.v[rb]);
+                        C.v[rb] = mfma(q[4], x.y, C.v[rb]);
+                        C.v[rb] = mfma(q[8], x.z, C.v[rb]);
+                        C.v[rb] = mfma(q[12], x.w, C.v[rb]);
+                    }
+                }
+                strip_store<B>(C, Y + (size_t)col0 * B, B);
+            }
+            return;
+        }
+        // D'(i): R_ii^T X_i = Y_i, forward over the rows that are not padding
+        const double *R = tile(t.i, t.i);
+        double *Y = btile(t.i);
+        const int64_t rem = nrow - (int64_t)t.i * B;
+        const int nloc = (int)(rem < B ? rem : B);
+        const int tid = threadIdx.x;
+        double *y = smem;  // B x 16
+        for (int g0 = 0; g0 < wb; g0 += 16) {
+            for (int idx = tid; idx < B * 16; idx += NT) {
+                const int r = idx % B, c = idx / B;
+                y[idx] = (r < nloc) ? Y[(size_t)(g0 + c) * B + r] : 0.0;
+            }
+            __syncthreads();
+            for (int cidx = 0; cidx < nloc; ++cidx) {
+                if (tid < 16) y[cidx + tid * B] = y[cidx + tid * B] / R[(size_t)cidx * B + cidx];
+                __syncthreads();
+                const int rest = nloc - cidx - 1;
+                for (int idx = tid; idx < rest * 16; idx += NT) {
+                    const int r = cidx + 1 + idx % rest, c = idx / rest;
+                    y[r + c * B] -= R[(size_t)r * B + cidx] * y[cidx + c * B];
+                }
+                __syncthreads();
+            }
+            for (int idx = tid; idx < B * 16; idx += NT) {
+                const int r = idx % B, c = idx / B;
+                Y[(size_t)(g0 + c) * B + r] = y[idx];
+            }
+            __syncthreads();
+        }
+    }
+};
+
 // ===========================================================================
 // The persistent scheduler: every workgroup repeatedly takes the
 // highest-priority ready task, runs it, and releases its successors; a
@@ -1070,8 +1222,8 @@ struct TrsmBody {
 // graph's order; returns how many.
 template <class G, class Body>
 __device__ __forceinline__ int early_successors(const G &, const Body &, const Task &) { return 0; }
-template <int B, int IB>
-__device__ __forceinline__ int early_successors(const FactorGraph &g, const FactorBody<B, IB> &b, const Task &t) {
+template <int B, int IB, bool F32>
+__device__ __forceinline__ int early_successors(const FactorGraph &g, const FactorBody<B, IB, F32> &b, const Task &t) {
     if (!b.prog || (t.kind != GEQRT && t.kind != TSQRT)) return 0;
     const int chain = t.i + 1 < g.p ? 1 : 0;
     if (t.kind == GEQRT) return chain;
@@ -1248,6 +1400,83 @@ __global__ void k_eye(double *Q, int64_t ldq, int64_t m) {
 }
 
 // d_info: smallest 1-based index k with R(k,k) == 0, else 0.
+// ---- FP64 residual kernels of least-squares refinement -------------------
+// F = B - Rv - A X (m x nrhs, all column-major); the sum over A's columns is
+// split over gridDim.y blocks of columns into Part (gridDim.y x m x nrhs),
+// which k_resid_reduce adds in a fixed order.
+constexpr int kResidChunks = 16;
+__global__ void k_resid_partial(const double *A, int64_t lda, int64_t m, int64_t n, const double *X, int64_t ldx,
+                                int nrhs, double *Part) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int64_t per = (n + gridDim.y - 1) / gridDim.y, j0 = blockIdx.y * per, j1 = min(n, j0 + per);
+    for (int c0 = 0; c0 < nrhs; c0 += 4) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t j = j0; j < j1; ++j) {
+            const double a = A[j * lda + i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c0 + c < nrhs) acc[c] += a * X[(c0 + c) * ldx + j];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c0 + c < nrhs) Part[((int64_t)blockIdx.y * nrhs + c0 + c) * m + i] = acc[c];
+    }
+}
+__global__ void k_resid_reduce(const double *Bm, int64_t ldb, const double *Rv, int64_t m, int nrhs, int chunks,
+                               const double *Part, double *F) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * nrhs) return;
+    const int64_t i = idx % m, c = idx / m;
+    double s = 0.0;
+    for (int k = 0; k < chunks; ++k) s += Part[((int64_t)k * nrhs + c) * m + i];
+    F[c * m + i] = Bm[c * ldb + i] - Rv[c * m + i] - s;
+}
+// G = -A^T Rv (n x nrhs): one block per column of A, a fixed-order tree sum.
+__global__ void k_neg_atr(const double *A, int64_t lda, int64_t m, const double *Rv, int nrhs, double *G, int64_t n) {
+    __shared__ double red[NT];
+    const int64_t j = blockIdx.x;
+    for (int c = 0; c < nrhs; ++c) {
+        double s = 0.0;
+        for (int64_t i = threadIdx.x; i < m; i += NT) s += A[j * lda + i] * Rv[c * m + i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = NT / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) G[c * n + j] = -red[0];
+        __syncthreads();
+    }
+}
+// Tiles of B (p tiles of b x wb): U = D - H on the first n rows, zero below;
+// then D's first n rows <- H (the vector [h; d2] of the augmented system).
+__global__ void k_aug_combine(double *Dt, const double *Ht, double *Ut, int b, int wb, int64_t n, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t tile = idx / ((int64_t)b * wb), e = idx % ((int64_t)b * wb);
+    const int64_t row = tile * b + e % b;
+    if (row < n) {
+        Ut[idx] = Dt[idx] - Ht[idx];
+        Dt[idx] = Ht[idx];
+    } else {
+        Ut[idx] = 0.0;
+    }
+}
+// Y (rows x nrhs, column-major, ld rows) += the first `rows` rows of tiles Bt.
+__global__ void k_tiles_add_to_cm(const double *Bt, int b, int wb, double *Y, int64_t rows, int nrhs) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * nrhs) return;
+    const int64_t r = idx % rows, c = idx / rows;
+    Y[c * rows + r] += Bt[(r / b) * b * wb + c * b + r % b];
+}
+__global__ void k_copy_cm(const double *S, int64_t lds, double *D, int64_t ldd, int64_t rows, int nrhs, double scale) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * nrhs) return;
+    const int64_t r = idx % rows, c = idx / rows;
+    D[c * ldd + r] = S ? scale * S[c * lds + r] : 0.0;
+}
+
 __global__ void k_diag_info(const double *W, int p, int b, int64_t n, int32_t *info) {
     __shared__ int32_t best;
     if (threadIdx.x == 0) best = 0x7fffffff;
@@ -1312,6 +1541,7 @@ Sizes sizes_of(int64_t m, int64_t n, int64_t nrhs, int b) {
     if (nrhs > 0) {
         nt = std::max(nt, ApplyGraph(z.p, z.q, cdiv(wb_of(nrhs), kStripCols), true).num_tasks());
         nt = std::max(nt, TrsmGraph(z.q).num_tasks());
+        nt = std::max(nt, TrsmTGraph(z.q).num_tasks());
     }
     z.sched_bytes = align256(sched_bytes(nt));
     z.prog_bytes = align256(z.p * z.q * 4);
@@ -1345,6 +1575,7 @@ int cu_count() {
 std::vector<int64_t> serial_order(const FactorGraph &g);
 std::vector<int64_t> serial_order(const ApplyGraph &g);
 std::vector<int64_t> serial_order(const TrsmGraph &g);
+std::vector<int64_t> serial_order(const TrsmTGraph &g);
 
 template <class G, class Body>
 tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, const tqr_options *opt,
@@ -1439,13 +1670,21 @@ std::vector<int64_t> serial_order(const TrsmGraph &g) {
     // G(i,j) needs D(j): rows are solved bottom-up, so D(j) precedes every G(i,j)
     return out;
 }
+std::vector<int64_t> serial_order(const TrsmTGraph &g) {
+    std::vector<int64_t> out;
+    for (int64_t i = 0; i < g.q; ++i) {
+        for (int64_t j = 0; j < i; ++j) out.push_back(g.encode_g(i, j));
+        out.push_back(g.encode_d(i));
+    }
+    return out;
+}
 
 // The factorisation body; with inner block 16 in persistent mode the R_kk
 // chain is pipelined (progress words cleared here, on the stream).
-template <int B, int IB>
-FactorBody<B, IB> factor_body(double *W, double *T, double *Vd, const Sizes &z, void *work, void *sched,
-                              const tqr_options *opt, hipStream_t stream) {
-    FactorBody<B, IB> body{W, T, Vd, (int)z.p};
+template <int B, int IB, bool F32 = false>
+FactorBody<B, IB, F32> factor_body(double *W, double *T, double *Vd, const Sizes &z, void *work, void *sched,
+                                   const tqr_options *opt, hipStream_t stream) {
+    FactorBody<B, IB, F32> body{W, T, Vd, (int)z.p};
     const bool serial = opt && opt->mode == TQR_MODE_SERIAL;
     if (IB == 16 && !serial) {
         body.prog = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(work) + z.prog_offset());
@@ -1552,8 +1791,19 @@ tqr_status factor_impl(int64_t m, int64_t n, double *A, int64_t lda, double *T, 
     hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, A, lda, m, n, W,
                        (int)z.p, B, B);
     FactorGraph g(z.p, z.q, B);
-    const FactorBody<B, IB> body = factor_body<B, IB>(W, T, Vd, z, work, sched, opt, stream);
-    tqr_status st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
+    tqr_status st;
+    if constexpr (IB == 16) {
+        if (opt && opt->precision == TQR_PRECISION_FP32_UPDATES) {
+            const FactorBody<B, IB, true> body = factor_body<B, IB, true>(W, T, Vd, z, work, sched, opt, stream);
+            st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
+        } else {
+            const FactorBody<B, IB> body = factor_body<B, IB>(W, T, Vd, z, work, sched, opt, stream);
+            st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
+        }
+    } else {
+        const FactorBody<B, IB> body = factor_body<B, IB>(W, T, Vd, z, work, sched, opt, stream);
+        st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
+    }
     if (st != TQR_OK) return st;
     if (back_to_cm)
         hipLaunchKernelGGL(k_tiles_to_cm, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, W, (int)z.p, B, B,
@@ -1568,8 +1818,9 @@ tqr_status apply_impl(bool trans, int64_t m, int64_t n, int64_t nrhs, const doub
                       const tqr_options *opt = nullptr) {
     int32_t *status = opt ? opt->status : nullptr;
     const int64_t p = cdiv(m, B), q = cdiv(n, B), wb = wb_of(nrhs);
-    hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)p, 1), dim3(256), 0, stream, Bm, ldb, m, nrhs, Bt, (int)p, B,
-                       (int)wb);
+    if (Bm)  // else Bt already holds B in tiles
+        hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)p, 1), dim3(256), 0, stream, Bm, ldb, m, nrhs, Bt, (int)p, B,
+                           (int)wb);
     ApplyGraph g(p, q, cdiv(wb, kStripCols), trans);
     tqr_status st;
     if (trans)
@@ -1587,6 +1838,15 @@ tqr_status trsm_impl(int64_t m, int64_t n, int64_t nrhs, const double *W, double
     const int64_t p = cdiv(m, B), q = cdiv(n, B), wb = wb_of(nrhs);
     TrsmGraph g(q);
     return run_graph(g, TrsmBody<B>{W, Bt, (int)p, (int)wb, n}, sched, (size_t)B * 16 * 8, opt, stream,
+                     opt ? opt->status : nullptr, 1);
+}
+
+template <int B>
+tqr_status trsmt_impl(int64_t m, int64_t n, int64_t nrhs, const double *W, double *Bt, void *sched, hipStream_t stream,
+                      const tqr_options *opt = nullptr) {
+    const int64_t p = cdiv(m, B), q = cdiv(n, B), wb = wb_of(nrhs);
+    TrsmTGraph g(q);
+    return run_graph(g, TrsmTBody<B>{W, Bt, (int)p, (int)wb, n}, sched, (size_t)B * 16 * 8, opt, stream,
                      opt ? opt->status : nullptr, 1);
 }
 
@@ -1615,6 +1875,8 @@ tqr_status check_opts(const tqr_options *o) {
     if (o->policy != TQR_POLICY_PAPER && o->policy != TQR_POLICY_LOOKAHEAD && o->policy != TQR_POLICY_COLUMN)
         return -11;
     if (o->workgroups < 0) return -11;
+    if (o->precision != TQR_PRECISION_FP64 && o->precision != TQR_PRECISION_FP32_UPDATES) return -11;
+    if (o->reserved != 0) return -11;
     return TQR_OK;
 }
 
@@ -1651,6 +1913,8 @@ tqr_status tqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, int tile_
     if (!work) return set_err(-8, "work is null");
     if (work_bytes < tqr_workspace_bytes(m, n, 0, tile_b, inner_ib)) return set_err(-9, "work_bytes too small");
     if (check_opts(options) != TQR_OK) return set_err(-11, "bad tqr_options");
+    if (options && options->precision == TQR_PRECISION_FP32_UPDATES && inner_ib != 16)
+        return set_err(-11, "TQR_PRECISION_FP32_UPDATES needs inner_ib 16");
     return dispatch(tile_b, inner_ib, [&](auto BB, auto II) {
         return factor_impl<decltype(BB)::value, decltype(II)::value>(m, n, A, lda, T, work, stream, options, true);
     });
@@ -1804,6 +2068,134 @@ tqr_status tqr_solve_ls_ex(int64_t m, int64_t n, int64_t nrhs, double *A, int64_
 }
 
 // ---- graph introspection ----------------------------------------------------
+// Workspace of the mixed solver: the solve layout (tiles, dense V, B tiles,
+// scheduler, progress words), two more B-tile buffers, x, r, f, g and the
+// partial sums of A x.
+struct MixedSizes {
+    Sizes z;
+    int64_t ht, ut, xv, rv, f, g, part, total;
+};
+static MixedSizes mixed_sizes(int64_t m, int64_t n, int64_t nrhs, int b) {
+    MixedSizes s;
+    s.z = sizes_of(m, n, nrhs, b);
+    const int64_t bt = s.z.btiles_bytes;
+    s.ht = s.z.total;
+    s.ut = s.ht + bt;
+    s.xv = s.ut + bt;
+    s.rv = s.xv + align256(n * nrhs * 8);
+    s.f = s.rv + align256(m * nrhs * 8);
+    s.g = s.f + align256(m * nrhs * 8);
+    s.part = s.g + align256(n * nrhs * 8);
+    s.total = s.part + align256((int64_t)kResidChunks * m * nrhs * 8);
+    return s;
+}
+
+int64_t tqr_ls_mixed_workspace_bytes(int64_t m, int64_t n, int64_t nrhs, int tile_b) {
+    if (m < 0 || n < 0 || m < n || nrhs < 1 || !(tile_b == 64 || tile_b == 128 || tile_b == 256)) return -1;
+    return mixed_sizes(m, n, nrhs, tile_b).total;
+}
+
+tqr_status tqr_solve_ls_mixed(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+                              int64_t ldb, double *X, int64_t ldx, int tile_b, int iterations, double *T, void *work,
+                              int64_t work_bytes, int32_t *d_info, hipStream_t stream, const tqr_options *options) {
+    g_err.clear();
+    if (m < 0 || m < n) return set_err(-1, "m must be >= max(n, 0)");
+    if (n < 0) return set_err(-2, "n must be >= 0");
+    if (nrhs < 1) return set_err(-3, "nrhs must be >= 1");
+    if (!A && m * n > 0) return set_err(-4, "A is null");
+    if (lda < std::max<int64_t>(1, m)) return set_err(-5, "lda < max(1, m)");
+    if (!B) return set_err(-6, "B is null");
+    if (ldb < std::max<int64_t>(1, m)) return set_err(-7, "ldb < max(1, m)");
+    if (!X) return set_err(-8, "X is null");
+    if (ldx < std::max<int64_t>(1, n)) return set_err(-9, "ldx < max(1, n)");
+    if (!(tile_b == 64 || tile_b == 128 || tile_b == 256)) return set_err(-10, "tile_b must be 64, 128 or 256");
+    if (iterations < 0 || iterations > 50) return set_err(-11, "iterations must be in 0..50");
+    if (!T) return set_err(-12, "T is null");
+    if (!work) return set_err(-13, "work is null");
+    const MixedSizes ms = mixed_sizes(std::max<int64_t>(m, 1), std::max<int64_t>(n, 1), nrhs, tile_b);
+    if (work_bytes < ms.total) return set_err(-14, "work_bytes too small");
+    if (!d_info) return set_err(-15, "d_info is null");
+    if (check_opts(options) != TQR_OK || (options && options->mode != TQR_MODE_PERSISTENT))
+        return set_err(-16, "bad options (struct_size, precision, or a mode other than TQR_MODE_PERSISTENT)");
+    if (m == 0 || n == 0) {
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_info, 0);
+        if (n > 0)
+            hipLaunchKernelGGL(k_copy_cm, dim3((unsigned)cdiv(n * nrhs, 256)), dim3(256), 0, stream, nullptr, 0, X, ldx,
+                               n, (int)nrhs, 0.0);
+        HIPCHK(hipGetLastError());
+        return TQR_OK;
+    }
+    tqr_options o{};
+    if (options) o = *options;
+    else {
+        o.struct_size = (int32_t)sizeof(tqr_options);
+        o.precision = TQR_PRECISION_FP32_UPDATES;
+    }
+    o.trace = nullptr;
+    o.event_begin = o.event_end = nullptr;
+    if (options && options->event_begin) HIPCHK(hipEventRecord((hipEvent_t)options->event_begin, stream));
+    const Sizes &z = ms.z;
+    char *wbase = reinterpret_cast<char *>(work);
+    double *W = reinterpret_cast<double *>(wbase);
+    double *Vd = reinterpret_cast<double *>(wbase + z.tiles_bytes);
+    double *Bt = reinterpret_cast<double *>(wbase + z.tiles_bytes + z.vd_bytes);
+    void *sched = wbase + z.tiles_bytes + z.vd_bytes + z.btiles_bytes;
+    double *Ht = reinterpret_cast<double *>(wbase + ms.ht), *Ut = reinterpret_cast<double *>(wbase + ms.ut);
+    double *Xv = reinterpret_cast<double *>(wbase + ms.xv), *Rv = reinterpret_cast<double *>(wbase + ms.rv);
+    double *F = reinterpret_cast<double *>(wbase + ms.f), *G = reinterpret_cast<double *>(wbase + ms.g);
+    double *Part = reinterpret_cast<double *>(wbase + ms.part);
+    const int64_t wb = wb_of(nrhs), btot = z.p * tile_b * wb;
+    const unsigned gm = (unsigned)cdiv(m * nrhs, 256), gn = (unsigned)cdiv(n * nrhs, 256);
+    tqr_status st = dispatch(tile_b, 16, [&](auto BB, auto) -> tqr_status {
+        constexpr int Bv = decltype(BB)::value;
+        hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, A, lda, m, n, W,
+                           (int)z.p, Bv, Bv);
+        FactorGraph g(z.p, z.q, Bv);
+        tqr_status s1;
+        if (o.precision == TQR_PRECISION_FP32_UPDATES) {
+            const FactorBody<Bv, 16, true> body = factor_body<Bv, 16, true>(W, T, Vd, z, work, sched, &o, stream);
+            s1 = run_graph(g, body, sched, TileKernels<Bv, 16>::LDS_BYTES, &o, stream, o.status);
+        } else {
+            const FactorBody<Bv, 16> body = factor_body<Bv, 16>(W, T, Vd, z, work, sched, &o, stream);
+            s1 = run_graph(g, body, sched, TileKernels<Bv, 16>::LDS_BYTES, &o, stream, o.status);
+        }
+        if (s1 != TQR_OK) return s1;
+        hipLaunchKernelGGL(k_diag_info, dim3(1), dim3(256), 0, stream, W, (int)z.p, Bv, n, d_info);
+        hipLaunchKernelGGL(k_copy_cm, dim3(gn), dim3(256), 0, stream, nullptr, 0, Xv, n, n, (int)nrhs, 0.0);
+        hipLaunchKernelGGL(k_copy_cm, dim3(gm), dim3(256), 0, stream, B, ldb, Rv, m, m, (int)nrhs, 1.0);
+        for (int it = 0; it < iterations; ++it) {
+            // FP64 residuals of the augmented system
+            hipLaunchKernelGGL(k_resid_partial, dim3((unsigned)cdiv(m, 256), kResidChunks), dim3(256), 0, stream, A, lda,
+                               m, n, Xv, n, (int)nrhs, Part);
+            hipLaunchKernelGGL(k_resid_reduce, dim3(gm), dim3(256), 0, stream, B, ldb, Rv, m, (int)nrhs, kResidChunks,
+                               Part, F);
+            hipLaunchKernelGGL(k_neg_atr, dim3((unsigned)n), dim3(NT), 0, stream, A, lda, m, Rv, (int)nrhs, G, n);
+            // d = Q^T f (in Bt);  h = R^{-T} g (in Ht)
+            s1 = apply_impl<Bv, 16>(true, m, n, nrhs, T, W, Vd, F, m, Bt, sched, stream, &o);
+            if (s1 != TQR_OK) return s1;
+            hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, 1), dim3(256), 0, stream, G, n, n, nrhs, Ht, (int)z.p,
+                               Bv, (int)wb);
+            s1 = trsmt_impl<Bv>(m, n, nrhs, W, Ht, sched, stream, &o);
+            if (s1 != TQR_OK) return s1;
+            // u = d[0:n] - h;  Bt <- [h; d[n:m]]
+            hipLaunchKernelGGL(k_aug_combine, dim3((unsigned)cdiv(btot, 256)), dim3(256), 0, stream, Bt, Ht, Ut, Bv,
+                               (int)wb, n, btot);
+            s1 = trsm_impl<Bv>(m, n, nrhs, W, Ut, sched, stream, &o);  // dx = R^{-1} u
+            if (s1 != TQR_OK) return s1;
+            s1 = apply_impl<Bv, 16>(false, m, n, nrhs, T, W, Vd, nullptr, 0, Bt, sched, stream, &o);  // dr
+            if (s1 != TQR_OK) return s1;
+            hipLaunchKernelGGL(k_tiles_add_to_cm, dim3(gn), dim3(256), 0, stream, Ut, Bv, (int)wb, Xv, n, (int)nrhs);
+            hipLaunchKernelGGL(k_tiles_add_to_cm, dim3(gm), dim3(256), 0, stream, Bt, Bv, (int)wb, Rv, m, (int)nrhs);
+        }
+        hipLaunchKernelGGL(k_copy_cm, dim3(gn), dim3(256), 0, stream, Xv, n, X, ldx, n, (int)nrhs, 1.0);
+        return TQR_OK;
+    });
+    if (st != TQR_OK) return st;
+    if (options && options->event_end) HIPCHK(hipEventRecord((hipEvent_t)options->event_end, stream));
+    HIPCHK(hipGetLastError());
+    return TQR_OK;
+}
+
 int64_t tqr_batch_plan(int64_t count, tqr_batch_problem *problems) {
     g_err.clear();
     if (count < 0) return set_err(-1, "count < 0");

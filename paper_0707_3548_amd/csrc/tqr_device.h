@@ -222,6 +222,107 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
 }
 
 // ---------------------------------------------------------------------------
+// FP32 precision tier of the update kernels (LARFB / SSRFB): the strip is
+// held as floats in the same rows-by-lane layout as Strip<B>, V and T are
+// staged in LDS as floats, and every product runs on v_mfma_f32_16x16x4f32
+// (twice the FP64 matrix rate).  That instruction takes its operands in the
+// lanes of the FP64 one (lane l supplies A[l%16][l/16] and B[l/16][l%16]) but
+// returns D[4(l/16)+i][l%16] in element i, four consecutive rows per lane.
+// Results that feed the next product keep that layout (W, op(T) W), and the
+// final C -= V W reads V's rows through the permutation 4a+b -> 4b+a, so that
+// output element i of lane l lands on strip row 16rb + 4i + l/16, as stored.
+// ---------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int B>
+struct StripF {
+    f4 v[B / 16];
+};
+
+template <int B>
+__device__ __forceinline__ void strip_load_f(StripF<B> &s, const double *col0, int ld) {
+    const int l = lane_id();
+    const double *p = col0 + (size_t)(l & 15) * ld + (l >> 4);
+#pragma unroll
+    for (int rb = 0; rb < B / 16; ++rb) {
+        const d4 x = ld4s(p + 16 * rb, 4);
+        s.v[rb] = f4{(float)x.x, (float)x.y, (float)x.z, (float)x.w};
+    }
+}
+
+template <int B>
+__device__ __forceinline__ void strip_store_f(const StripF<B> &s, double *col0, int ld) {
+    const int l = lane_id();
+    double *p = col0 + (size_t)(l & 15) * ld + (l >> 4);
+#pragma unroll
+    for (int rb = 0; rb < B / 16; ++rb)
+        st4s(p + 16 * rb, 4, d4{(double)s.v[rb].x, (double)s.v[rb].y, (double)s.v[rb].z, (double)s.v[rb].w});
+}
+
+// The block reflector of one inner block of 16 columns (the forms of
+// panel_update) applied to a float strip.  Vl: V(row, a) = Vl[a * ldv + row]
+// (floats); Tl: T(r, c) = Tl[16 c + r] (floats).  The TS form's top rows stay
+// FP64 in memory: W takes their float value and they are updated in FP64 by
+// the float correction.
+template <int B, bool TRANS, bool TS>
+__device__ __forceinline__ void panel_update_f32(StripF<B> &C, double *top, const float *Vl, int ldv, const float *Tl,
+                                                 int c0, bool write_top = true) {
+    const int l = lane_id();
+    const int rb0 = TS ? 0 : c0 / 16;
+    // W = V^T C; k-slice (rb, r): rows 16rb + 4r + {0..3}; W row a in lane
+    // group a/4, element a%4
+    f4 W = {0.0f, 0.0f, 0.0f, 0.0f};
+    const float *vp = Vl + (l & 15) * ldv + (l >> 4);
+#pragma unroll
+    for (int rb = 0; rb < B / 16; ++rb) {
+        if (!TS && rb < rb0) continue;
+        const float *q = vp + 16 * rb;
+        W = mfma32(q[0], C.v[rb].x, W);
+        W = mfma32(q[4], C.v[rb].y, W);
+        W = mfma32(q[8], C.v[rb].z, W);
+        W = mfma32(q[12], C.v[rb].w, W);
+    }
+    double *tp = nullptr;
+    d4 t = {0.0, 0.0, 0.0, 0.0};
+    if (TS) {
+        tp = top + (size_t)(l & 15) * B + c0 + 4 * (l >> 4);
+        t = d4{tp[0], tp[1], tp[2], tp[3]};
+        W += f4{(float)t.x, (float)t.y, (float)t.z, (float)t.w};
+    }
+    // W2 = op(T) W; k-slice r: W rows {4j + r}; A[d][j] = op(T)[d][4j + r]
+    f4 W2 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float a = TRANS ? Tl[(l & 15) * 16 + 4 * (l >> 4) + r] : Tl[(4 * (l >> 4) + r) * 16 + (l & 15)];
+        W2 = mfma32(a, W[r], W2);
+    }
+    if (TS && write_top) {
+        tp[0] = t.x - (double)W2.x;
+        tp[1] = t.y - (double)W2.y;
+        tp[2] = t.z - (double)W2.z;
+        tp[3] = t.w - (double)W2.w;
+    }
+    W2 = -W2;
+    // C -= V W2; output row d of an MFMA is strip row 16rb + perm(d),
+    // perm(4a + b) = 4b + a
+    const int pr = 4 * (l & 3) + ((l & 15) >> 2);
+    const float *vq = Vl + 4 * (l >> 4) * ldv + pr;
+#pragma unroll
+    for (int rb = 0; rb < B / 16; ++rb) {
+        if (!TS && rb < rb0) continue;
+        const float *q = vq + 16 * rb;
+        C.v[rb] = mfma32(q[0], W2.x, C.v[rb]);
+        C.v[rb] = mfma32(q[ldv], W2.y, C.v[rb]);
+        C.v[rb] = mfma32(q[2 * ldv], W2.z, C.v[rb]);
+        C.v[rb] = mfma32(q[3 * ldv], W2.w, C.v[rb]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Panel factorisation in LDS.  P holds hp rows and IB columns (ld = ldp);
 // column jj's reflector has its pivot in row jj and acts on rows jj..hp-1.
 // For GEQRT the panel is rows c0..b-1 of the diagonal tile; for TSQRT it is

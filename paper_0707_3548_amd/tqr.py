@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libtqr.so")
 MODE_PERSISTENT, MODE_SERIAL = 0, 1
 POLICY_PAPER, POLICY_LOOKAHEAD, POLICY_COLUMN = 0, 1, 2
 TQR_EDEVICE, TQR_EABORTED = -1000, -1001
+PRECISION_FP64, PRECISION_FP32_UPDATES = 0, 1
 
 
 class TqrError(RuntimeError):
@@ -42,6 +43,8 @@ class Options(ctypes.Structure):
         ("timeout_ticks", ctypes.c_int64),
         ("event_begin", ctypes.c_void_p),
         ("event_end", ctypes.c_void_p),
+        ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -85,6 +88,11 @@ def lib() -> ctypes.CDLL:
         L.tqr_solve_ls.restype = i32
         L.tqr_solve_ls_ex.argtypes = [i64, i64, i64, dp, i64, dp, i64, i32, i32, dp, vp, i64, vp, vp, ctypes.POINTER(Options)]
         L.tqr_solve_ls_ex.restype = i32
+        L.tqr_ls_mixed_workspace_bytes.argtypes = [i64, i64, i64, i32]
+        L.tqr_ls_mixed_workspace_bytes.restype = i64
+        L.tqr_solve_ls_mixed.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64, i32, i32, dp, vp, i64, vp, vp,
+                                         ctypes.POINTER(Options)]
+        L.tqr_solve_ls_mixed.restype = i32
         L.tqr_batch_plan.argtypes = [i64, ctypes.POINTER(BatchProblem)]
         L.tqr_batch_plan.restype = i64
         L.tqr_factor_batched.argtypes = [i64, vp, vp, i64, vp, ctypes.c_int32, vp]
@@ -150,10 +158,11 @@ class Workspace:
 def factor(A: torch.Tensor, tile_b: int, inner_ib: int, ws: Workspace | None = None, *, workgroups: int = 0,
            mode: int = MODE_PERSISTENT, policy: int = POLICY_PAPER, trace: torch.Tensor | None = None,
            status: torch.Tensor | None = None, abort_flag=None, timeout_ticks: int = 0,
-           events=None):
+           events=None, precision: int = PRECISION_FP64):
     """In-place tiled QR of the column-major A; returns (A, T).  ``events`` is
     an optional pair of raw hipEvent_t handles recorded around the scheduler
-    launch (see HipEvents)."""
+    launch (see HipEvents); ``precision`` PRECISION_FP32_UPDATES runs the
+    trailing updates on the FP32 matrix cores."""
     m, n = A.shape
     lda = _ld(A)
     if ws is None:
@@ -161,7 +170,7 @@ def factor(A: torch.Tensor, tile_b: int, inner_ib: int, ws: Workspace | None = N
     opt = Options(ctypes.sizeof(Options), workgroups, mode, policy,
                   trace.data_ptr() if trace is not None else None,
                   abort_flag, status.data_ptr() if status is not None else None, timeout_ticks,
-                  events[0] if events else None, events[1] if events else None)
+                  events[0] if events else None, events[1] if events else None, precision, 0)
     rc = lib().tqr_factor_ex(m, n, A.data_ptr(), lda, tile_b, inner_ib, ws.T.data_ptr(), ws.work.data_ptr(),
                              ws.work.numel(), _stream(), ctypes.byref(opt))
     _check("tqr_factor", rc)
@@ -226,6 +235,35 @@ def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None, *, workgroups:
                                 ws.T.data_ptr(), ws.work.data_ptr(), ws.work.numel(), info.data_ptr(), _stream())
         _check("tqr_solve_ls", rc)
     return B, info
+
+
+# ---- mixed-precision least squares -------------------------------------------------
+
+def solve_ls_mixed(A: torch.Tensor, B: torch.Tensor, tile_b: int, iterations: int = 5, *,
+                   precision: int = PRECISION_FP32_UPDATES, workgroups: int = 0, work: torch.Tensor | None = None,
+                   X: torch.Tensor | None = None, info: torch.Tensor | None = None, events=None):
+    """min ||A X - B|| with the factor's trailing updates in FP32 and FP64
+    refinement of the augmented system (tqr_solve_ls_mixed).  A and B are
+    column-major and left unchanged; returns (X, T, info)."""
+    m, n = A.shape
+    nrhs = B.shape[1]
+    nb = int(lib().tqr_ls_mixed_workspace_bytes(m, n, nrhs, tile_b))
+    if nb < 0:
+        raise ValueError("unsupported sizes or tile_b")
+    if work is None or work.numel() < nb:
+        work = torch.empty(nb, dtype=torch.uint8, device=A.device)
+    if X is None:
+        X = torch.empty((nrhs, max(n, 1)), dtype=torch.float64, device=A.device).t()[:n]
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    T = torch.zeros(max(t_elems(m, n, tile_b, 16), 1), dtype=torch.float64, device=A.device)
+    opt = Options(ctypes.sizeof(Options), workgroups, MODE_PERSISTENT, POLICY_PAPER, None, None, None, 0,
+                  events[0] if events else None, events[1] if events else None, precision, 0)
+    rc = lib().tqr_solve_ls_mixed(m, n, nrhs, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), X.data_ptr(),
+                                  max(1, X.stride(1) if nrhs > 1 else n), tile_b, iterations, T.data_ptr(),
+                                  work.data_ptr(), work.numel(), info.data_ptr(), _stream(), ctypes.byref(opt))
+    _check("tqr_solve_ls_mixed", rc)
+    return X, T, info
 
 
 # ---- batched factorisation ------------------------------------------------------

@@ -1,0 +1,125 @@
+"""FP32 precision tier (trailing updates on the FP32 matrix cores) and the
+mixed-precision least-squares solver with FP64 refinement of the augmented
+system.
+
+Tolerances: the FP32-update factor is compared with the unblocked FP64 oracle
+to FP32 accuracy (R to 1e-4 relative, ||A - QR|| / ||A|| to 50 sqrt(n) u32),
+while Q stays orthogonal to FP64 accuracy (every reflector comes from the
+FP64 panels and is applied in FP64).  The refined least-squares solution
+must meet the FP64 bounds of the FP64 solver's own test: backward error
+< 1e-14 and forward error < cond * 1e-13 against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+
+U32 = 2.0 ** -24
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_mixed_workspace_query():
+    from paper_0707_3548_amd import tqr
+    L = tqr.lib()
+    assert L.tqr_ls_mixed_workspace_bytes(100, 50, 2, 64) > 0
+    assert L.tqr_ls_mixed_workspace_bytes(100, 50, 2, 32) == -1
+    assert L.tqr_ls_mixed_workspace_bytes(10, 50, 2, 64) == -1
+    assert L.tqr_ls_mixed_workspace_bytes(100, 50, 0, 64) == -1
+
+
+def test_mixed_argument_checks():
+    import ctypes
+    from paper_0707_3548_amd import tqr
+    L = tqr.lib()
+    a = ctypes.c_void_p(4096)
+    args = [100, 50, 1, a, 100, a, 100, a, 50, 64, 3, a, a, 1 << 30, a, None, None]
+    def rc(**kw):
+        v = list(args)
+        names = ["m", "n", "nrhs", "A", "lda", "B", "ldb", "X", "ldx", "tile_b", "iters", "T", "work", "wb", "info"]
+        for k, x in kw.items():
+            v[names.index(k)] = x
+        return L.tqr_solve_ls_mixed(*v)
+    assert rc(m=10) == -1
+    assert rc(n=-1) == -2
+    assert rc(nrhs=0) == -3
+    assert rc(lda=99) == -5
+    assert rc(ldb=10) == -7
+    assert rc(ldx=10) == -9
+    assert rc(tile_b=32) == -10
+    assert rc(iters=51) == -11
+    assert rc(wb=100) == -14
+    assert rc(info=None) == -15
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m,n,b", [(512, 512, 64), (600, 400, 128), (1000, 300, 256), (257, 129, 64)])
+def test_fp32_updates_factor(m, n, b):
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    print(f"case fp32-updates factor m={m} n={n} b={b}", flush=True)
+    A = workloads.gaussian(m, n, seed=31)
+    dA = tqr.fortran(torch.from_numpy(A).cuda())
+    ws = tqr.Workspace(m, n, 0, b, 16)
+    tqr.factor(dA, b, 16, ws, precision=tqr.PRECISION_FP32_UPDATES)
+    torch.cuda.synchronize()
+    F = dA.cpu().numpy()
+    R = np.triu(F[:n, :])
+    _, R_or = oracle.qr(A)
+    assert oracle.rel_fro(oracle.sign_normalize(R), R_or) < 1e-4
+    E = torch.zeros((n, m), dtype=torch.float64, device="cuda").t()
+    E[torch.arange(n), torch.arange(n)] = 1.0
+    tqr.apply_q(dA, ws.T, E, b, 16)
+    torch.cuda.synchronize()
+    Q = E.cpu().numpy()
+    assert oracle.orth_error(Q) <= 10 * n * oracle.EPS
+    assert oracle.fact_error(A, Q, R) <= 50 * np.sqrt(n) * U32
+    # and it is not the FP64 factor: the tier really ran in FP32
+    dB = tqr.fortran(torch.from_numpy(A).cuda())
+    tqr.factor(dB, b, 16)
+    torch.cuda.synchronize()
+    assert not torch.equal(dA, dB)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m,n,b,nrhs,cond", [(512, 256, 64, 1, 1e2), (600, 400, 64, 3, 1e5), (1000, 300, 128, 2, 1e3),
+                                             (777, 500, 256, 1, 1e4)])
+def test_mixed_ls_reaches_fp64_accuracy(m, n, b, nrhs, cond):
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    print(f"case mixed LS m={m} n={n} b={b} nrhs={nrhs} cond={cond}", flush=True)
+    A, Bh, _ = workloads.ls_problem(m, n, cond, seed=32, nrhs=nrhs)
+    dA = tqr.fortran(torch.from_numpy(A).cuda())
+    dB = tqr.fortran(torch.from_numpy(Bh).cuda())
+    A0, B0 = dA.clone(), dB.clone()
+    X, _, info = tqr.solve_ls_mixed(dA, dB, b, iterations=6)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    assert torch.equal(dA, A0) and torch.equal(dB, B0)
+    Xh = X.cpu().numpy()
+    Xo, _ = oracle.lstsq(A, Bh)
+    assert np.linalg.norm(Xh - Xo) / np.linalg.norm(Xo) < cond * 1e-13
+    for c in range(nrhs):
+        assert oracle.ls_backward_error(A, Xh[:, c], Bh[:, c]) < 1e-14
+
+
+@pytest.mark.gpu
+def test_mixed_ls_with_fp64_factor_and_zero_iterations():
+    """iterations = 0 returns x = 0; with an FP64 factor one step already
+    reaches the semi-normal-equations solution and a few more the bound."""
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    print("case mixed LS fp64 factor", flush=True)
+    A, Bh, _ = workloads.ls_problem(300, 200, 1e2, seed=33, nrhs=1)
+    dA = tqr.fortran(torch.from_numpy(A).cuda())
+    dB = tqr.fortran(torch.from_numpy(Bh).cuda())
+    X0, _, _ = tqr.solve_ls_mixed(dA, dB, 64, iterations=0)
+    torch.cuda.synchronize()
+    assert float(X0.abs().max()) == 0.0
+    X, _, info = tqr.solve_ls_mixed(dA, dB, 64, iterations=3, precision=tqr.PRECISION_FP64)
+    torch.cuda.synchronize()
+    assert oracle.ls_backward_error(A, X.cpu().numpy()[:, 0], Bh[:, 0]) < 1e-14
