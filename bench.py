@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=32)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--batch-count", type=int, default=20000)
     return ap.parse_args()
 
@@ -172,6 +173,84 @@ def serving_leg(count: int):
     return out
 
 
+def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
+    """The FP32 precision tier: (1) the same 8192x8192 factorisation with the
+    trailing updates on the FP32 matrix cores (FP64 panels), timed like the
+    headline; (2) least squares 16384x4096 (A = U diag(s) V^T, cond 1e5,
+    one right-hand side) solved in FP64 and mixed (FP32-update factor + 5
+    FP64 refinement steps), both with inputs in HBM, and the relative
+    difference of the two solutions."""
+    import numpy as np
+    import torch
+    from paper_0707_3548_amd import tqr, workloads
+
+    out = {}
+    m, n = A_host.shape
+    src = tqr.fortran(torch.from_numpy(A_host).cuda())
+    ws = tqr.Workspace(m, n, 0, b, ib)
+    copies = [src.clone() for _ in range(2)]
+    ts = []
+    for s in range(steps + 2):
+        dA = copies[s % 2]
+        dA.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tqr.factor(dA, b, ib, ws, precision=tqr.PRECISION_FP32_UPDATES)
+        e1.record()
+        torch.cuda.synchronize()
+        if s >= 2:
+            ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[len(ts) // 2]
+    fl = 2.0 * n * n * (m - n / 3.0)
+    out["fp32_updates_factor"] = {"workload": f"{m}x{n} N(0,1), tile_b={b}, inner_ib={ib}, LARFB/SSRFB on FP32 MFMA, "
+                                              "GEQRT/TSQRT in FP64", "ms_per_step": round(ms, 3),
+                                  "gflops_standard": round(fl / ms / 1e6, 1), "speedup_vs_fp64": round(fp64_ms / ms, 3)}
+    del copies, ws, src
+    torch.cuda.empty_cache()
+
+    lm, ln, cond = 16384, 4096, 1e5
+    Ah, Bh, _ = workloads.ls_request(lm, ln, 1, cond, seed=41)
+    dA0 = tqr.fortran(torch.from_numpy(Ah).cuda())
+    dB0 = tqr.fortran(torch.from_numpy(Bh).cuda())
+    work = torch.empty(int(tqr.lib().tqr_ls_mixed_workspace_bytes(lm, ln, 1, 256)), dtype=torch.uint8, device="cuda")
+    ws64 = tqr.Workspace(lm, ln, 1, 256, 16)
+
+    def time_it(fn, reps=3):
+        t = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            fn(e0, e1)
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return sorted(t[1:])[len(t[1:]) // 2]
+
+    def run64(e0, e1):
+        dA, dB = dA0.clone(), dB0.clone()
+        e0.record()
+        tqr.solve_ls(dA, dB, 256, 16, ws64)
+        e1.record()
+        run64.X = dB
+
+    def runmx(e0, e1):
+        e0.record()
+        X, _, info = tqr.solve_ls_mixed(dA0, dB0, 256, iterations=5, work=work)
+        e1.record()
+        runmx.X, runmx.info = X, info
+
+    t64 = time_it(run64)
+    tmx = time_it(runmx)
+    x64 = run64.X[:ln].cpu().numpy()
+    xmx = runmx.X.cpu().numpy()
+    out["least_squares"] = {"workload": f"{lm}x{ln}, A = U diag(s) V^T with cond {cond:g}, one right-hand side, "
+                                        "b = A x + 1e-6 noise", "fp64_ms": round(t64, 3), "mixed_ms": round(tmx, 3),
+                            "mixed_iterations": 5, "speedup": round(t64 / tmx, 3),
+                            "rel_diff_mixed_vs_fp64": float(np.linalg.norm(xmx - x64) / np.linalg.norm(x64)),
+                            "info": int(runmx.info.item())}
+    print(f"bench: mixed tier: factor {ms:.2f} ms (fp64 {fp64_ms:.2f}); LS fp64 {t64:.2f} ms, mixed {tmx:.2f} ms",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def batched_leg(count: int, steps: int = 5):
     """The batched factorisation: ``count`` independent N(0,1) problems, m
     log-uniform in [16, 512], n uniform in [8, m], one launch per batch
@@ -280,6 +359,11 @@ def main():
         del Ft, wst
         torch.cuda.empty_cache()
 
+    mixed_out = None
+    if not args.no_mixed:
+        print("bench: mixed-precision tier", file=sys.stderr, flush=True)
+        mixed_out = mixed_legs(A, b, ib, wall_ms)
+
     batched_out = None
     if not args.no_batched:
         print("bench: batched", file=sys.stderr, flush=True)
@@ -325,6 +409,7 @@ def main():
         "cpu_baseline": cpu,
         "check": check,
         "tall_skinny": tall,
+        "mixed_precision": mixed_out,
         "batched": batched_out,
         "serving": serving_out,
     }
