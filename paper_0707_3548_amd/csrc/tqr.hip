@@ -601,14 +601,15 @@ struct TileKernels {
         double *Rd = smem + 32 * LDV + 512;
         const int w = __builtin_amdgcn_readfirstlane(wave_id());
         const bool t0 = threadIdx.x == 0;
-        // block s (with the lookahead panel s+1) touches row blocks s and s+1
-        // of R_kk: it may start once the predecessor has finished s+2 of them
+        // block s touches row block s of R_kk and, through the lookahead
+        // panel s+1, the diagonal block of row block s+1; the predecessor
+        // touches neither after its own block s, so block s may start once
+        // the predecessor has published s+1 finished row blocks
         if (pp.prev) {
             if (t0) pipe_wait(pp, 1);
             __syncthreads();
         }
         if (w == 0) tsqrt16_panel(Akk, Aik, Tik, 0, nullptr, nullptr, Vb[0], Tb[0], Rd);
-        if (pp.prev && t0) pipe_wait(pp, min(2, NB));
         __syncthreads();
         if (NB == 1 && pp.mine && t0) pipe_publish(pp, 1);
 #pragma unroll 1
@@ -624,7 +625,7 @@ struct TileKernels {
                     strip_store<B>(C, Aik + (size_t)16 * j * B, B);
                 }
             }
-            if (pp.prev && t0) pipe_wait(pp, min(s + 3, NB));
+            if (pp.prev && t0) pipe_wait(pp, min(s + 2, NB));
             __syncthreads();
             if (pp.mine && t0) pipe_publish(pp, s + 2 == NB ? NB : s + 1);
         }
