@@ -215,7 +215,7 @@ typedef struct tqr_batch_problem {
     int64_t m, n, lda;   /* m >= n >= 0, lda >= max(1, m) */
     double *A;           /* device, column-major; overwritten as by tqr_factor */
     double *T;           /* device, tqr_t_elems(m, n, tile_b, 16) doubles, written */
-    int32_t tile_b;      /* 16, 32 or 64 */
+    int32_t tile_b;      /* 16, 32, 64 or 128 */
     int32_t reserved;    /* 0 */
     int64_t work_offset; /* byte offset of the problem's tiles in work: set by tqr_batch_plan */
 } tqr_batch_problem;

@@ -17,7 +17,7 @@ from typing import Callable, Sequence
 
 # (lowest n of the bucket, tile size); buckets run up to the next entry's n
 DEFAULT_TABLE = [(0, 16), (32, 32), (64, 64)]
-CANDIDATES = (16, 32, 64)
+CANDIDATES = (16, 32, 64, 128)
 BUCKETS = (0, 16, 32, 64, 128, 256)
 
 

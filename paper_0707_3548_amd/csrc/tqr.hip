@@ -1748,7 +1748,8 @@ __device__ void batch_one(const tqr_batch_problem &pr, char *work, double *smem)
 }
 
 constexpr size_t kBatchLds =
-    std::max(TileKernels<16, 16>::LDS_BYTES, std::max(TileKernels<32, 16>::LDS_BYTES, TileKernels<64, 16>::LDS_BYTES));
+    std::max(std::max(TileKernels<16, 16>::LDS_BYTES, TileKernels<32, 16>::LDS_BYTES),
+             std::max(TileKernels<64, 16>::LDS_BYTES, TileKernels<128, 16>::LDS_BYTES));
 
 // Persistent launch over the problems; *counter (cleared before the launch)
 // hands out problem indices.  Every workgroup leaves once the counter passes
@@ -1768,6 +1769,7 @@ __global__ void __launch_bounds__(NT) k_batched(const tqr_batch_problem *problem
         case 16: batch_one<16>(pr, work, smem); break;
         case 32: batch_one<32>(pr, work, smem); break;
         case 64: batch_one<64>(pr, work, smem); break;
+        case 128: batch_one<128>(pr, work, smem); break;
         default:
             if (threadIdx.x == 0 && status) *status = (int32_t)(pi + 1);
             break;
@@ -2204,12 +2206,13 @@ int64_t tqr_batch_plan(int64_t count, tqr_batch_problem *problems) {
     int64_t off = 256;  // the first 256 bytes hold the problem counter
     for (int64_t i = 0; i < count; ++i) {
         tqr_batch_problem &pr = problems[i];
-        const bool tile_ok = pr.tile_b == 16 || pr.tile_b == 32 || pr.tile_b == 64;
+        const bool tile_ok = pr.tile_b == 16 || pr.tile_b == 32 || pr.tile_b == 64 || pr.tile_b == 128;
         const bool bad = pr.n < 0 || pr.m < pr.n || pr.lda < std::max<int64_t>(1, pr.m) || !tile_ok ||
                          (pr.m * pr.n > 0 && (!pr.A || !pr.T)) || pr.reserved != 0;
         if (bad) {
             static thread_local char msg[128];
-            snprintf(msg, sizeof msg, "problem %lld: bad m, n, lda, tile_b (16, 32, 64), A, T or reserved", (long long)i);
+            snprintf(msg, sizeof msg, "problem %lld: bad m, n, lda, tile_b (16, 32, 64, 128), A, T or reserved",
+                     (long long)i);
             return set_err(-2, msg);
         }
         pr.work_offset = off;

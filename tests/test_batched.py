@@ -31,6 +31,7 @@ def test_plan_offsets_and_checks():
     assert offs[1] - offs[0] == -(-((3 * 2 + 2) * 256 * 8) // 256) * 256
     assert _plan([(10, 20)], [16])[0] == -2          # m < n
     assert _plan([(40, 17)], [48])[0] == -2          # tile size
+    assert _plan([(40, 17)], [256])[0] == -2
     assert _plan([(40, 17)], [16], null_a=True)[0] == -2
     assert b"problem 0" in tqr.lib().tqr_last_error_string()
     assert tqr.lib().tqr_batch_plan(-1, None) == -1
@@ -54,7 +55,7 @@ def test_tile_table_and_tuner():
 
     def time_batch(shapes, b):
         n = shapes[0][1]
-        return {16: 3.0, 32: 1.0, 64: 2.0}[b] if n < 64 else {16: 5.0, 32: 4.0, 64: 1.0}[b]
+        return {16: 3.0, 32: 1.0, 64: 2.0, 128: 6.0}[b] if n < 64 else {16: 5.0, 32: 4.0, 64: 1.0, 128: 3.0}[b]
 
     table = autotune.tune(sample, time_batch)
     assert table == [(0, 32), (64, 64)]
