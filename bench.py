@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--tile-b", type=int, default=256)
     ap.add_argument("--inner-ib", type=int, default=16)
-    ap.add_argument("--policy", choices=["paper", "lookahead", "column"], default="paper")
+    ap.add_argument("--policy", choices=["paper", "lookahead", "column"], default="column")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle's CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tall", action="store_true")
@@ -395,7 +395,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"FP64 tiled QR of one {n}x{n} N(0,1) matrix, tile_b={b}, inner_ib={ib}, "
-                               f"persistent task-graph scheduler ({args.policy} priorities)",
+                               f"persistent task-graph scheduler ({args.policy} priorities"
+                               + (": GEQRT > TSQRT > updates by their column's distance from the current panel)"
+                                  if args.policy == "column" else ")"),
                    "m": n, "n": n, "tile_b": b, "inner_ib": ib},
         "rates": {"gflops_standard_2n2(m-n/3)": round(value, 2),
                   "gflops_tiled_executed": round(exe / (wall_ms * 1e-3) / 1e9, 2),

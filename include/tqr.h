@@ -110,8 +110,9 @@ typedef struct tqr_options {
 #define TQR_MODE_SERIAL 1      /* one launch per task, in Algorithm 1 order (reference order) */
 #define TQR_POLICY_PAPER 0     /* ready tasks by kind: GEQRT > TSQRT > LARFB > SSRFB (Sec. 3.3) */
 #define TQR_POLICY_LOOKAHEAD 1 /* as PAPER, but updates of the next panel's tile column first */
-#define TQR_POLICY_COLUMN 2    /* as PAPER, with LARFB/SSRFB ordered by their tile column's distance
-                                  j - k from the panel (nearer first, six levels) */
+#define TQR_POLICY_COLUMN 2    /* GEQRT > TSQRT > LARFB/SSRFB ordered by the distance of their tile
+                                  column from the next panel (the later of step k+1 and the GEQRT
+                                  started last; nearer first, six levels) */
 #define TQR_PRECISION_FP64 0         /* every kernel in FP64 */
 #define TQR_PRECISION_FP32_UPDATES 1 /* LARFB and SSRFB (the trailing updates, nearly all the
                                         flops) on the FP32 matrix cores; GEQRT/TSQRT (norms,

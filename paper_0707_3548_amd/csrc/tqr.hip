@@ -66,7 +66,8 @@ struct SchedState {
     uint32_t done;    // number of finished tasks without successors
     int32_t status;   // 0, or TQR_EABORTED
     uint32_t nsinks;  // number of tasks without successors (set by k_sched_seed)
-    uint32_t pad0[60];
+    int32_t panel;    // factorisation: GEQRT tasks started so far (priority reference)
+    uint32_t pad0[59];
     uint64_t ht[8];   // per priority level: (tail << 32) | head of its queue
     uint32_t pad1[48];
     uint64_t idle[kMaxWorkers / 64];  // bit w set: worker w waits on its mailbox
@@ -116,17 +117,18 @@ __global__ void k_sched_init(G g, Sched s) {
         s.st->done = 0;
         s.st->status = 0;
         s.st->nsinks = 0;
+        s.st->panel = 0;
     }
 }
 
 template <class G>
-__device__ __host__ inline int level_of(const G &, const Task &, int) { return 0; }
+__device__ __host__ inline int level_of(const G &, const Task &, int, int = 0) { return 0; }
 template <>
-__device__ __host__ inline int level_of<FactorGraph>(const FactorGraph &g, const Task &t, int policy) {
-    return g.level(t, policy);
+__device__ __host__ inline int level_of<FactorGraph>(const FactorGraph &g, const Task &t, int policy, int panel) {
+    return g.level(t, policy, panel);
 }
 template <>
-__device__ __host__ inline int level_of<TrsmGraph>(const TrsmGraph &, const Task &t, int) {
+__device__ __host__ inline int level_of<TrsmGraph>(const TrsmGraph &, const Task &t, int, int) {
     return t.kind == 0 ? 0 : 1;
 }
 
@@ -1236,7 +1238,7 @@ constexpr int kReadyCap = 64;  // ready successors collected per task before pub
 template <class G, class Body>
 __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunOpts o) {
     extern __shared__ double smem[];
-    __shared__ int32_t s_task, s_cont, s_nready, s_nover;
+    __shared__ int32_t s_task, s_cont, s_nready, s_nover, s_panel;
     __shared__ int32_t s_ready[kReadyCap];
     __shared__ int8_t s_lvl[kReadyCap];
     const int tid = threadIdx.x;
@@ -1268,6 +1270,11 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         // for a continuation the thread that found it ready already did
         if (!cont) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const Task task = g.decode(t);
+        if constexpr (std::is_same<G, FactorGraph>::value) {
+            // GEQRT(k) starts in order of k: k+1 panels have started
+            if (task.kind == GEQRT && tid == 0)
+                __hip_atomic_store(&s.st->panel, task.k + 1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+        }
         // successors that follow this task's progress may start as soon as
         // it has started
         const int nearly = early_successors(g, body, task);
@@ -1277,7 +1284,7 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
                 const int64_t e = g.successor(task, n);
                 if (__hip_atomic_fetch_add(&s.cnt[e], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) == 1) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-                    push_one(s, level_of(g, g.decode(e), o.policy), (int32_t)e);
+                    push_one(s, level_of(g, g.decode(e), o.policy, flag_load(&s.st->panel)), (int32_t)e);
                     ++pushed;
                 }
             }
@@ -1287,7 +1294,9 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         body.run(task, smem);
         const uint64_t t_body = o.trace ? rt_clock() : 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (tid == 0) s_panel = flag_load(&s.st->panel);
         __syncthreads();
+        const int panel = s_panel;
         if (o.trace && tid == 0) {
             int64_t *tr = o.trace + kTraceFields * (int64_t)t;
             tr[0] = (int64_t)t_pop;
@@ -1307,7 +1316,7 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
             if (old == 1) {
                 // acquire the other predecessors' writes, release them onward
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-                const int lvl = level_of(g, g.decode(sidx), o.policy);
+                const int lvl = level_of(g, g.decode(sidx), o.policy, panel);
                 const int slot = atomicAdd(&s_nready, 1);
                 if (slot < kReadyCap) {
                     s_ready[slot] = (int32_t)sidx;

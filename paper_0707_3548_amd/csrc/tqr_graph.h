@@ -155,14 +155,19 @@ struct FactorGraph {
 
     // priority level: 0 is served first.  Policy 0 (the paper's): by kind;
     // 1: the updates of tile column k+1 (the next panel) before the other
-    // updates; 2: updates by the distance j-k of their tile column from the
-    // panel, levels 2..7 (the last holds every column from k+6 on).
-    TQR_HD int level(const Task &t, int policy) const {
+    // updates; 2: updates by the distance of their tile column j from the
+    // next panel, levels 2..7 (the last holds every column from 6 on).  The
+    // next panel is column k+1 for a task of step k, or `panel` (the number
+    // of GEQRT tasks started so far) when the factorisation is further
+    // ahead: an update whose column the panels are approaching becomes
+    // more urgent than its step alone says.
+    TQR_HD int level(const Task &t, int policy, int panel = 0) const {
         if (t.kind == GEQRT) return 0;
         if (t.kind == TSQRT) return 1;
         if (policy == 2) {
-            const int d = t.j - t.k - 1;
-            return 2 + (d < 5 ? d : 5);
+            const int ref = panel > t.k + 1 ? panel : t.k + 1;
+            const int d = t.j - ref;
+            return 2 + (d < 0 ? 0 : (d < 5 ? d : 5));
         }
         if (t.kind == LARFB) return (policy == 1 && t.j == t.k + 1) ? 2 : 3;
         return (policy == 1 && t.j == t.k + 1) ? 2 : 4;
