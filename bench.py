@@ -195,7 +195,7 @@ def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
         dA.copy_(src)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        tqr.factor(dA, b, ib, ws, precision=tqr.PRECISION_FP32_UPDATES)
+        tqr.factor(dA, b, ib, ws, precision=tqr.PRECISION_FP32_UPDATES, policy=tqr.POLICY_COLUMN)
         e1.record()
         torch.cuda.synchronize()
         if s >= 2:
@@ -227,13 +227,13 @@ def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
     def run64(e0, e1):
         dA, dB = dA0.clone(), dB0.clone()
         e0.record()
-        tqr.solve_ls(dA, dB, 256, 16, ws64)
+        tqr.solve_ls(dA, dB, 256, 16, ws64, policy=tqr.POLICY_COLUMN)
         e1.record()
         run64.X = dB
 
     def runmx(e0, e1):
         e0.record()
-        X, _, info = tqr.solve_ls_mixed(dA0, dB0, 256, iterations=5, work=work)
+        X, _, info = tqr.solve_ls_mixed(dA0, dB0, 256, iterations=5, work=work, policy=tqr.POLICY_COLUMN)
         e1.record()
         runmx.X, runmx.info = X, info
 

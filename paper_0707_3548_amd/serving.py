@@ -192,7 +192,7 @@ class GpuExecutor:
             ws = tqr.Workspace(req.m, req.n, req.nrhs, b, ib, self.device)
             info = torch.zeros(1, dtype=torch.int32, device=self.device)
             w = workers_for(req.m, req.n, b, self.device_slots)
-            tqr.solve_ls(dA, dB, b, ib, ws, workgroups=w, info=info)
+            tqr.solve_ls(dA, dB, b, ib, ws, workgroups=w, info=info, policy=tqr.POLICY_COLUMN)
             pl["X"].copy_(dB[: req.n].t(), non_blocking=True)
             pl["info"].copy_(info, non_blocking=True)
             ev = torch.cuda.Event()

@@ -213,18 +213,19 @@ def form_q(A, T, tile_b, inner_ib, Q: torch.Tensor | None = None, ws: Workspace 
 
 
 def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None, *, workgroups: int = 0,
-             status: torch.Tensor | None = None, info: torch.Tensor | None = None):
+             status: torch.Tensor | None = None, info: torch.Tensor | None = None, policy: int = POLICY_PAPER):
     """min ||A X - B||: A overwritten by its factors, X in B[0:n].  Returns
     (B, info tensor on the device).  ``workgroups`` > 0 caps the persistent
-    workers of every phase (tqr_solve_ls_ex)."""
+    workers of every phase; ``policy`` picks the priority policy
+    (tqr_solve_ls_ex)."""
     m, n = A.shape
     nrhs = B.shape[1]
     if ws is None:
         ws = Workspace(m, n, nrhs, tile_b, inner_ib, A.device)
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
-    if workgroups > 0 or status is not None:
-        opt = Options(ctypes.sizeof(Options), workgroups, MODE_PERSISTENT, POLICY_PAPER, None, None,
+    if workgroups > 0 or status is not None or policy != POLICY_PAPER:
+        opt = Options(ctypes.sizeof(Options), workgroups, MODE_PERSISTENT, policy, None, None,
                       status.data_ptr() if status is not None else None, 0, None, None)
         rc = lib().tqr_solve_ls_ex(m, n, nrhs, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), tile_b, inner_ib,
                                    ws.T.data_ptr(), ws.work.data_ptr(), ws.work.numel(), info.data_ptr(), _stream(),
@@ -241,7 +242,8 @@ def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None, *, workgroups:
 
 def solve_ls_mixed(A: torch.Tensor, B: torch.Tensor, tile_b: int, iterations: int = 5, *,
                    precision: int = PRECISION_FP32_UPDATES, workgroups: int = 0, work: torch.Tensor | None = None,
-                   X: torch.Tensor | None = None, info: torch.Tensor | None = None, events=None):
+                   X: torch.Tensor | None = None, info: torch.Tensor | None = None, events=None,
+                   policy: int = POLICY_PAPER):
     """min ||A X - B|| with the factor's trailing updates in FP32 and FP64
     refinement of the augmented system (tqr_solve_ls_mixed).  A and B are
     column-major and left unchanged; returns (X, T, info)."""
@@ -257,7 +259,7 @@ def solve_ls_mixed(A: torch.Tensor, B: torch.Tensor, tile_b: int, iterations: in
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
     T = torch.zeros(max(t_elems(m, n, tile_b, 16), 1), dtype=torch.float64, device=A.device)
-    opt = Options(ctypes.sizeof(Options), workgroups, MODE_PERSISTENT, POLICY_PAPER, None, None, None, 0,
+    opt = Options(ctypes.sizeof(Options), workgroups, MODE_PERSISTENT, policy, None, None, None, 0,
                   events[0] if events else None, events[1] if events else None, precision, 0)
     rc = lib().tqr_solve_ls_mixed(m, n, nrhs, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), X.data_ptr(),
                                   max(1, X.stride(1) if nrhs > 1 else n), tile_b, iterations, T.data_ptr(),
