@@ -422,6 +422,7 @@ constexpr int kTraceFields = 8;
 
 struct RunOpts {
     int64_t *trace;
+    int64_t ntrace;  // tasks with a trace record (the paper's tasks; helper tasks have none)
     const volatile int32_t *abort_flag;
     int64_t timeout;
     int policy;
@@ -439,13 +440,24 @@ struct RunOpts {
 struct Pipe {
     int32_t *prev, *mine, *status;
     uint64_t deadline;
+    // TSQRT(i,k) and its helper: panels stored (pv), blocks the helper has
+    // applied to its strips (hb), and the claim of those strips (claim: 0
+    // open, 1 the TSQRT kept them, 2 the helper took them); null without a
+    // helper
+    int32_t *pv = nullptr, *hb = nullptr, *claim = nullptr;
+    // the predecessor TSQRT's helper words (row block s of R_kk is final
+    // when the predecessor has finished it and, if its helper took strips,
+    // the helper has applied block s)
+    int32_t *prev_hb = nullptr, *prev_claim = nullptr;
 };
+
+constexpr uint64_t kClaimTicks = 2000;  // how long a TSQRT waits for its helper (device clock ticks)
 
 // Thread 0: waits until the predecessor has finished `target` row blocks,
 // then acquires its writes.
-__device__ void pipe_wait(const Pipe &pp, int target) {
+__device__ void pipe_wait_on(const Pipe &pp, const int32_t *word, int target) {
     uint32_t n = 0;
-    while (flag_load(pp.prev) < target) {
+    while (flag_load(word) < target) {
         if (flag_load(pp.status) != 0) return;
         if (rt_clock() > pp.deadline || ++n > kMaxSpins) {
             __hip_atomic_store(pp.status, (int32_t)TQR_EABORTED, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
@@ -455,13 +467,26 @@ __device__ void pipe_wait(const Pipe &pp, int target) {
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
+__device__ __forceinline__ void pipe_wait(const Pipe &pp, int target) { pipe_wait_on(pp, pp.prev, target); }
 
-// Thread 0, after a workgroup barrier: releases the workgroup's writes and
-// publishes that `count` row blocks are finished.
-__device__ void pipe_publish(const Pipe &pp, int count) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(pp.mine, count, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+// Thread 0 of a chain task: waits until row blocks 0 .. rows-1 of R_kk are
+// final (the predecessor's own progress, then its helper's; the claim is
+// settled before the predecessor publishes anything).
+__device__ void pipe_wait_rows(const Pipe &pp, int rows, int nb) {
+    pipe_wait(pp, rows);
+    if (pp.prev_claim && flag_load(pp.prev_claim) == 2) {
+        const int t = rows < nb - 2 ? rows : nb - 2;
+        if (t > 0) pipe_wait_on(pp, pp.prev_hb, t);
+    }
 }
+
+// Thread 0, after a workgroup barrier (or after its own wave's stores):
+// releases those writes and publishes `count`.
+__device__ void pipe_publish_on(int32_t *word, int count) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(word, count, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+}
+__device__ __forceinline__ void pipe_publish(const Pipe &pp, int count) { pipe_publish_on(pp.mine, count); }
 
 // ===========================================================================
 // Tile kernels (bodies run by one workgroup)
@@ -597,47 +622,116 @@ struct TileKernels {
     // TSQRT with ib = 16, organised as geqrt16: wave 0 factors [R_kk block;
     // A_ik panel] pairs (ts_panel16) with lookahead, waves 1..3 apply each
     // block to the columns right of the next panel.
+    // Strips [help_split(), NB) of a TSQRT go to its helper when the helper
+    // claims them (about 5/16 of the strips: the helper's four waves then
+    // carry as much trailing work per block as the TSQRT's three).
+    __device__ __forceinline__ static int help_split() { return NB - (5 * NB) / 16; }
+
     __device__ __forceinline__ static void tsqrt16(double *Akk, double *Aik, double *Tik, double *smem, const Pipe &pp) {
         double *Vb[2] = {smem, smem + 16 * LDV};
         double *Tb[2] = {smem + 32 * LDV, smem + 32 * LDV + 256};
         double *Rd = smem + 32 * LDV + 512;
         const int w = __builtin_amdgcn_readfirstlane(wave_id());
         const bool t0 = threadIdx.x == 0;
+        __shared__ int32_t s_split;
         // block s touches row block s of R_kk and, through the lookahead
         // panel s+1, the diagonal block of row block s+1; the predecessor
         // touches neither after its own block s, so block s may start once
         // the predecessor has published s+1 finished row blocks
         if (pp.prev) {
-            if (t0) pipe_wait(pp, 1);
+            if (t0) pipe_wait_rows(pp, 1, NB);
             __syncthreads();
         }
-        if (w == 0) tsqrt16_panel(Akk, Aik, Tik, 0, nullptr, nullptr, Vb[0], Tb[0], Rd);
+        if (w == 0) {
+            tsqrt16_panel(Akk, Aik, Tik, 0, nullptr, nullptr, Vb[0], Tb[0], Rd, NB, pp);
+        } else if (w == 1 && lane_id() == 0) {
+            // while panel 0 is factored, give the helper (released when this
+            // task started) a moment to claim its strips; otherwise keep them
+            int32_t expect = 0;
+            if (pp.claim) {
+                const uint64_t until = rt_clock() + kClaimTicks;
+                while (flag_load(pp.claim) == 0 && rt_clock() < until) __builtin_amdgcn_s_sleep(1);
+                __hip_atomic_compare_exchange_strong(pp.claim, &expect, 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     TQR_FLAG_SCOPE);
+            }
+            s_split = expect == 2 ? help_split() : NB;
+        }
         __syncthreads();
+        const int split = __builtin_amdgcn_readfirstlane(s_split);
         if (NB == 1 && pp.mine && t0) pipe_publish(pp, 1);
 #pragma unroll 1
         for (int s = 0; s + 1 < NB; ++s) {
             double *Vs = Vb[s & 1], *Ts = Tb[s & 1];
             if (w == 0) {
-                tsqrt16_panel(Akk, Aik, Tik, s + 1, Vs, Ts, Vb[(s + 1) & 1], Tb[(s + 1) & 1], Rd);
+                tsqrt16_panel(Akk, Aik, Tik, s + 1, Vs, Ts, Vb[(s + 1) & 1], Tb[(s + 1) & 1], Rd, split, pp);
             } else {
-                for (int j = s + 1 + w; j < NB; j += NWAVES - 1) {
+                for (int j = s + 1 + w; j < split; j += NWAVES - 1) {
                     Strip<B> C;
                     strip_load<B>(C, Aik + (size_t)16 * j * B, B);
                     panel_update<B, 16, true, true>(C, Akk + (size_t)16 * j * B, Vs, LDV, Ts, 16 * s);
                     strip_store<B>(C, Aik + (size_t)16 * j * B, B);
                 }
             }
-            if (pp.prev && t0) pipe_wait(pp, min(s + 2, NB));
+            if (pp.prev && t0) pipe_wait_rows(pp, min(s + 2, NB), NB);
             __syncthreads();
+            // this task's part of row block s is final (the helper's part is
+            // published by the helper)
             if (pp.mine && t0) pipe_publish(pp, s + 2 == NB ? NB : s + 1);
         }
     }
 
+    // The helper of TSQRT(i,k): claims strips [help_split(), NB) of A_ik and
+    // applies every inner block to them as the TSQRT publishes its panels
+    // (pv), publishing the blocks applied (hb); the TSQRT applies the last
+    // block to each of those strips itself (the lookahead before its panel).
+    // The same operations in the same order on every column as without it.
+    __device__ __forceinline__ static void tsqrt16_helper(double *Akk, double *Aik, const double *Tik, double *smem,
+                                                          const Pipe &pp) {
+        __shared__ int32_t s_ok;
+        const bool t0 = threadIdx.x == 0;
+        const int w = __builtin_amdgcn_readfirstlane(wave_id());
+        if (t0) {
+            int32_t expect = 0;
+            s_ok = __hip_atomic_compare_exchange_strong(pp.claim, &expect, 2, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                        TQR_FLAG_SCOPE)
+                       ? 1
+                       : 0;
+        }
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(s_ok)) return;
+        const int split = help_split();
+        double *Vl = smem, *Tl = smem + (size_t)LDV * IB;
+#pragma unroll 1
+        for (int s = 0; s + 2 < NB; ++s) {
+            if (t0) {
+                // block s rewrites row block s of R_kk over the helper's
+                // strips: the predecessor (and its helper) must be done with
+                // it, and this task's panel s must be stored
+                if (pp.prev) pipe_wait_rows(pp, s + 1, NB);
+                pipe_wait_on(pp, pp.pv, s + 1);
+            }
+            __syncthreads();
+            stage(Aik, Tik, 16 * s, Vl, Tl);
+            __syncthreads();
+            for (int j = max(split, s + 2) + w; j < NB; j += NWAVES) {
+                Strip<B> C;
+                strip_load<B>(C, Aik + (size_t)16 * j * B, B);
+                panel_update<B, 16, true, true>(C, Akk + (size_t)16 * j * B, Vl, LDV, Tl, 16 * s);
+                strip_store<B>(C, Aik + (size_t)16 * j * B, B);
+            }
+            __syncthreads();
+            if (t0) pipe_publish_on(pp.hb, s + 1);
+        }
+    }
+
     __device__ __forceinline__ static void tsqrt16_panel(double *Akk, double *Aik, double *Tik, int j, const double *Vs,
-                                                         const double *Ts, double *Vn, double *Tn, double *Rd) {
+                                                         const double *Ts, double *Vn, double *Tn, double *Rd, int split,
+                                                         const Pipe &pp) {
         const int l = lane_id();
         const int cj = 16 * j;
         double *acol = Aik + (size_t)cj * B, *rcol = Akk + (size_t)cj * B;
+        // a helper strip has blocks 0 .. j-2 applied by the helper
+        if (j >= split && threadIdx.x == 0) pipe_wait_on(pp, pp.hb, j - 1);
         {
             Strip<B> C;
             strip_load<B>(C, acol, B);
@@ -676,6 +770,9 @@ struct TileKernels {
             if (r <= c) rcol[(size_t)c * B + cj + r] = Rd[idx];
             Tik[(size_t)cj * 16 + idx] = Tn[idx];
         }
+        // V and T of panel j are stored: for the helper and the SSRFB that
+        // follow this task
+        if (pp.pv && threadIdx.x == 0) pipe_publish_on(pp.pv, j + 1);
     }
 
     struct Lds {
@@ -833,15 +930,15 @@ struct TileKernels {
     // so that waiting for them does not wait for the prefetch.
     template <bool TRANS, bool TS>
     // With pp.prev (forward order only) the reflectors are those of a TSQRT
-    // still running: block s is read once that task has published
-    // max(s, 1) (its panel s is then factored and stored).
+    // still running: block s is read once that task has stored panel s
+    // (its panel word pp.prev reaches s + 1).
     __device__ __forceinline__ static void apply_dbuf(Strip<B> &C, double *Top, const double *V, const double *T,
                                                       int col0, bool owner, double *smem, const Pipe &pp = Pipe{}) {
         double *buf[2] = {smem, smem + STAGE_DOUBLES};
         const bool t0 = threadIdx.x == 0;
         StageRegs R;
         if (TRANS && pp.prev) {
-            if (t0) pipe_wait(pp, 1);
+            if (t0) pipe_wait(pp, min(2, NB));  // blocks 0 and 1
             __syncthreads();
         }
         stage_fetch(V, T, (TRANS ? 0 : NB - 1) * IB, R);
@@ -857,7 +954,7 @@ struct TileKernels {
             panel_update<B, IB, TRANS, TS>(C, TS ? Top + (size_t)col0 * B : nullptr, cur, LDV, cur + (size_t)LDV * IB,
                                            c0, owner, TS ? Wt : nullptr);
             if (si + 1 < NB) stage_commit(R, buf[(si + 1) & 1]);
-            if (TRANS && pp.prev && t0 && si + 2 < NB) pipe_wait(pp, si + 2);
+            if (TRANS && pp.prev && t0 && si + 2 < NB) pipe_wait(pp, si + 3);  // block si+2, fetched next
             __syncthreads();
         }
     }
@@ -945,7 +1042,7 @@ struct TileKernels {
         const bool t0 = threadIdx.x == 0;
         StageRegs R;
         if (TRANS && pp.prev) {
-            if (t0) pipe_wait(pp, 1);
+            if (t0) pipe_wait(pp, min(2, NB));
             __syncthreads();
         }
         stage_fetch(V, T, (TRANS ? 0 : NB - 1) * IB, R);
@@ -959,7 +1056,7 @@ struct TileKernels {
             panel_update_f32<B, TRANS, TS>(C, TS ? Top + (size_t)col0 * B : nullptr, cur, LDV, cur + (size_t)LDV * IB,
                                            c0, owner);
             if (si + 1 < NB) stage_commit_f(R, buf[(si + 1) & 1]);
-            if (TRANS && pp.prev && t0 && si + 2 < NB) pipe_wait(pp, si + 2);
+            if (TRANS && pp.prev && t0 && si + 2 < NB) pipe_wait(pp, si + 3);
             __syncthreads();
         }
     }
@@ -1005,18 +1102,30 @@ struct FactorBody {
     int32_t *prog = nullptr;
     int32_t *status = nullptr;
     int64_t wait_ticks = 0;
+    int q = 0;             // tile columns (the progress words are four p x q arrays)
+    bool helpers = false;  // TSQRT tasks have helper tasks in the graph
     __device__ double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
     __device__ Pipe pipe(const Task &t) const {
         Pipe pp{nullptr, nullptr, status, 0};
         if (prog) {
-            const int64_t row = (int64_t)t.k * p;
-            if (t.kind == TSQRT) {
-                pp.prev = prog + row + t.i - 1;
-                pp.mine = prog + row + t.i;  // read by TSQRT(i+1,k) and SSRFB(i,k+1,k)
+            // words of chain task (i,k): R_kk row blocks finished, panels
+            // stored, blocks applied by the helper, claim of the helper strips
+            const int64_t pq = (int64_t)p * q, row = (int64_t)t.k * p;
+            int32_t *panels = prog + pq + row, *helped = prog + 2 * pq + row, *claim = prog + 3 * pq + row;
+            if (t.kind == TSQRT || t.kind == TSQRT_HELP) {
+                pp.prev = prog + row + t.i - 1;  // the predecessor on the R_kk chain
+                pp.mine = t.kind == TSQRT ? prog + row + t.i : nullptr;  // read by TSQRT(i+1,k)
+                pp.pv = panels + t.i;
+                pp.hb = helped + t.i;
+                if (helpers) pp.claim = claim + t.i;
+                if (helpers && t.i - 1 > t.k) {
+                    pp.prev_hb = helped + t.i - 1;
+                    pp.prev_claim = claim + t.i - 1;
+                }
             } else if (t.kind == GEQRT) {
                 if (t.i + 1 < p) pp.mine = prog + row + t.i;
             } else if (t.kind == SSRFB && t.j == t.k + 1) {
-                pp.prev = prog + row + t.i;  // the TSQRT(i,k) whose reflectors it applies
+                pp.prev = panels + t.i;  // the panels of the TSQRT(i,k) whose reflectors it applies
             }
             pp.deadline = rt_clock() + (uint64_t)wait_ticks;
         }
@@ -1029,6 +1138,9 @@ struct FactorBody {
         switch (t.kind) {
         case GEQRT: K::geqrt(tile(t.k, t.k), tslot(t.k, t.k), vdiag(t.k), smem, pipe(t)); break;
         case TSQRT: K::tsqrt(tile(t.k, t.k), tile(t.i, t.k), tslot(t.i, t.k), smem, pipe(t)); break;
+        case TSQRT_HELP:
+            if constexpr (IB == 16) K::tsqrt16_helper(tile(t.k, t.k), tile(t.i, t.k), tslot(t.i, t.k), smem, pipe(t));
+            break;
         case LARFB:
             if constexpr (F32)
                 K::template larfb_f32<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem);
@@ -1230,7 +1342,8 @@ __device__ __forceinline__ int early_successors(const FactorGraph &g, const Fact
     if (!b.prog || (t.kind != GEQRT && t.kind != TSQRT)) return 0;
     const int chain = t.i + 1 < g.p ? 1 : 0;
     if (t.kind == GEQRT) return chain;
-    return chain + (t.k + 1 < g.q ? (int)g.S : 0);
+    if (t.kind != TSQRT) return 0;
+    return (g.helpers ? 1 : 0) + chain + (t.k + 1 < g.q ? (int)g.S : 0);
 }
 
 constexpr int kReadyCap = 64;  // ready successors collected per task before publishing
@@ -1297,7 +1410,7 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         if (tid == 0) s_panel = flag_load(&s.st->panel);
         __syncthreads();
         const int panel = s_panel;
-        if (o.trace && tid == 0) {
+        if (o.trace && tid == 0 && t < o.ntrace) {
             int64_t *tr = o.trace + kTraceFields * (int64_t)t;
             tr[0] = (int64_t)t_pop;
             tr[1] = (int64_t)t_acq;
@@ -1547,14 +1660,14 @@ Sizes sizes_of(int64_t m, int64_t n, int64_t nrhs, int b) {
     z.tiles_bytes = align256(z.p * z.q * b * b * 8);
     z.vd_bytes = align256(z.q * b * b * 8);
     z.btiles_bytes = nrhs > 0 ? align256(z.p * b * wb_of(nrhs) * 8) : 0;
-    int64_t nt = FactorGraph(z.p, z.q, b).num_tasks();
+    int64_t nt = FactorGraph(z.p, z.q, b, true).num_tasks();
     if (nrhs > 0) {
         nt = std::max(nt, ApplyGraph(z.p, z.q, cdiv(wb_of(nrhs), kStripCols), true).num_tasks());
         nt = std::max(nt, TrsmGraph(z.q).num_tasks());
         nt = std::max(nt, TrsmTGraph(z.q).num_tasks());
     }
     z.sched_bytes = align256(sched_bytes(nt));
-    z.prog_bytes = align256(z.p * z.q * 4);
+    z.prog_bytes = align256(4 * z.p * z.q * 4);
     z.total = z.tiles_bytes + z.vd_bytes + z.btiles_bytes + z.sched_bytes + z.prog_bytes;
     return z;
 }
@@ -1583,6 +1696,10 @@ int cu_count() {
 }
 
 std::vector<int64_t> serial_order(const FactorGraph &g);
+template <class G>
+int64_t trace_count(const G &g) { return g.num_tasks(); }
+template <>
+int64_t trace_count<FactorGraph>(const FactorGraph &g) { return g.num_paper_tasks(); }
 std::vector<int64_t> serial_order(const ApplyGraph &g);
 std::vector<int64_t> serial_order(const TrsmGraph &g);
 std::vector<int64_t> serial_order(const TrsmTGraph &g);
@@ -1628,6 +1745,7 @@ tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, 
     workers = std::min<int64_t>(std::min<int64_t>(workers, nt), kMaxWorkers);
     RunOpts ro;
     ro.trace = opt ? opt->trace : nullptr;
+    ro.ntrace = trace_count(g);
     ro.abort_flag = opt ? opt->abort_flag : nullptr;
     ro.timeout = (opt && opt->timeout_ticks > 0) ? opt->timeout_ticks : default_timeout_ticks();
     ro.policy = policy;
@@ -1700,7 +1818,12 @@ FactorBody<B, IB, F32> factor_body(double *W, double *T, double *Vd, const Sizes
         body.prog = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(work) + z.prog_offset());
         body.status = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(sched) + offsetof(SchedState, status));
         body.wait_ticks = (opt && opt->timeout_ticks > 0) ? opt->timeout_ticks : default_timeout_ticks();
-        const int64_t n = z.p * z.q;
+        body.q = (int)z.q;
+        // helpers shorten each TSQRT, which paces square problems; on tall
+        // ones the chain of TSQRTs down a column paces the run and a helper
+        // adds to every link of it
+        body.helpers = B >= 128 && z.p <= 2 * z.q;
+        const int64_t n = 4 * z.p * z.q;
         hipLaunchKernelGGL(k_fill_int, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, body.prog, n, 0);
     }
     return body;
@@ -1807,13 +1930,16 @@ tqr_status factor_impl(int64_t m, int64_t n, double *A, int64_t lda, double *T, 
     if constexpr (IB == 16) {
         if (opt && opt->precision == TQR_PRECISION_FP32_UPDATES) {
             const FactorBody<B, IB, true> body = factor_body<B, IB, true>(W, T, Vd, z, work, sched, opt, stream);
+            g.helpers = body.helpers;
             st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
         } else {
             const FactorBody<B, IB> body = factor_body<B, IB>(W, T, Vd, z, work, sched, opt, stream);
+            g.helpers = body.helpers;
             st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
         }
     } else {
         const FactorBody<B, IB> body = factor_body<B, IB>(W, T, Vd, z, work, sched, opt, stream);
+        g.helpers = body.helpers;
         st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
     }
     if (st != TQR_OK) return st;
@@ -2058,6 +2184,7 @@ tqr_status tqr_solve_ls_ex(int64_t m, int64_t n, int64_t nrhs, double *A, int64_
                            (int)z.p, Bv, Bv);
         FactorGraph g(z.p, z.q, Bv);
         const FactorBody<Bv, Iv> body = factor_body<Bv, Iv>(W, T, Vd, z, work, sched, po, stream);
+        g.helpers = body.helpers;
         tqr_status s1 = run_graph(g, body, sched, TileKernels<Bv, Iv>::LDS_BYTES, po, stream, po ? po->status : nullptr);
         if (s1 != TQR_OK) return s1;
         hipLaunchKernelGGL(k_tiles_to_cm, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, W, (int)z.p, Bv,
@@ -2166,9 +2293,11 @@ tqr_status tqr_solve_ls_mixed(int64_t m, int64_t n, int64_t nrhs, const double *
         tqr_status s1;
         if (o.precision == TQR_PRECISION_FP32_UPDATES) {
             const FactorBody<Bv, 16, true> body = factor_body<Bv, 16, true>(W, T, Vd, z, work, sched, &o, stream);
+            g.helpers = body.helpers;
             s1 = run_graph(g, body, sched, TileKernels<Bv, 16>::LDS_BYTES, &o, stream, o.status);
         } else {
             const FactorBody<Bv, 16> body = factor_body<Bv, 16>(W, T, Vd, z, work, sched, &o, stream);
+            g.helpers = body.helpers;
             s1 = run_graph(g, body, sched, TileKernels<Bv, 16>::LDS_BYTES, &o, stream, o.status);
         }
         if (s1 != TQR_OK) return s1;

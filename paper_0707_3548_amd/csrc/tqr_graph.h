@@ -40,7 +40,7 @@
 
 namespace tqr {
 
-enum Kind : int { GEQRT = 0, TSQRT = 1, LARFB = 2, SSRFB = 3 };
+enum Kind : int { GEQRT = 0, TSQRT = 1, LARFB = 2, SSRFB = 3, TSQRT_HELP = 4 };
 constexpr int kStripCols = 64;   // columns of one update strip (one workgroup)
 constexpr int kLevels = 8;       // ready-queue priority levels
 
@@ -55,8 +55,13 @@ TQR_HD int strips_of(int b) { return b > kStripCols ? b / kStripCols : 1; }
 // ---------------------------------------------------------------------------
 struct FactorGraph {
     int64_t p, q, K, S;
+    // With `helpers`, every TSQRT(i,k) has a helper task TSQRT_HELP(i,k)
+    // (released when the TSQRT starts, no successors) that may take over part
+    // of its trailing updates; helper ids follow the paper's tasks.
+    bool helpers;
 
-    TQR_HD FactorGraph(int64_t p_, int64_t q_, int b) : p(p_), q(q_), K(p_ < q_ ? p_ : q_), S(strips_of(b)) {}
+    TQR_HD FactorGraph(int64_t p_, int64_t q_, int b, bool helpers_ = false)
+        : p(p_), q(q_), K(p_ < q_ ? p_ : q_), S(strips_of(b)), helpers(helpers_) {}
 
     // tasks of step k: (p-k) + (q-k-1)(p-k) S
     TQR_HD int64_t step_size(int64_t k) const { return (p - k) * (1 + S * (q - k - 1)); }
@@ -65,7 +70,11 @@ struct FactorGraph {
         const int64_t alpha = 1 + S * (q - 1);
         return p * alpha * k - (alpha + p * S) * (k * (k - 1) / 2) + S * ((k - 1) * k * (2 * k - 1) / 6);
     }
-    TQR_HD int64_t num_tasks() const { return offset(K); }
+    TQR_HD int64_t num_paper_tasks() const { return offset(K); }
+    // TSQRT tasks of steps before k: the sum over k' < k of (p - 1 - k')
+    TQR_HD int64_t help_offset(int64_t k) const { return k * (p - 1) - k * (k - 1) / 2; }
+    TQR_HD int64_t num_tasks() const { return offset(K) + (helpers ? help_offset(K) : 0); }
+    TQR_HD int64_t encode_help(int64_t i, int64_t k) const { return offset(K) + help_offset(k) + (i - k - 1); }
 
     TQR_HD int64_t encode(int kind, int64_t i, int64_t j, int64_t k, int64_t c) const {
         const int64_t P = p - k;
@@ -80,6 +89,24 @@ struct FactorGraph {
     }
 
     TQR_HD Task decode(int64_t t) const {
+        if (t >= offset(K)) {
+            const int64_t h = t - offset(K);
+            int64_t lo = 0, hi = K - 1;  // largest k with help_offset(k) <= h
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) / 2;
+                if (help_offset(mid) <= h)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            Task r;
+            r.kind = TSQRT_HELP;
+            r.k = (int)lo;
+            r.j = (int)lo;
+            r.i = (int)(lo + 1 + (h - help_offset(lo)));
+            r.c = 0;
+            return r;
+        }
         int64_t lo = 0, hi = K - 1;  // largest k with offset(k) <= t
         while (lo < hi) {
             int64_t mid = (lo + hi + 1) / 2;
@@ -110,6 +137,7 @@ struct FactorGraph {
 
     TQR_HD int indegree(const Task &t) const {
         const int prev = t.k > 0 ? 1 : 0;
+        if (t.kind == TSQRT_HELP) return 1;
         switch (t.kind) {
         case GEQRT: return prev * (int)S;
         case TSQRT: return 1 + prev * (int)S;
@@ -120,8 +148,9 @@ struct FactorGraph {
 
     TQR_HD int num_successors(const Task &t) const {
         switch (t.kind) {
-        case GEQRT:
-        case TSQRT: return (t.i + 1 < p ? 1 : 0) + (int)((q - t.k - 1) * S);
+        case TSQRT_HELP: return 0;
+        case GEQRT: return (t.i + 1 < p ? 1 : 0) + (int)((q - t.k - 1) * S);
+        case TSQRT: return (helpers ? 1 : 0) + (t.i + 1 < p ? 1 : 0) + (int)((q - t.k - 1) * S);
         case LARFB: return t.k + 1 < p ? 1 : 0;
         default: return (t.i + 1 < p ? 1 : 0) + 1;
         }
@@ -133,6 +162,10 @@ struct FactorGraph {
         switch (t.kind) {
         case GEQRT:
         case TSQRT: {
+            if (t.kind == TSQRT && helpers) {
+                if (n == 0) return encode_help(t.i, k);
+                --n;
+            }
             if (t.i + 1 < p) {
                 if (n == 0) return encode(TSQRT, t.i + 1, k, k, 0);
                 --n;
@@ -163,7 +196,7 @@ struct FactorGraph {
     // more urgent than its step alone says.
     TQR_HD int level(const Task &t, int policy, int panel = 0) const {
         if (t.kind == GEQRT) return 0;
-        if (t.kind == TSQRT) return 1;
+        if (t.kind == TSQRT || t.kind == TSQRT_HELP) return 1;
         if (policy == 2) {
             const int ref = panel > t.k + 1 ? panel : t.k + 1;
             const int d = t.j - ref;
