@@ -542,19 +542,21 @@ struct TileKernels {
     // right of panel j on the matrix cores.  V and T of the last factored
     // block alternate between two LDS buffers; one barrier per block.
     __device__ __forceinline__ static void geqrt16(double *Akk, double *Tkk, double *Vkk, double *smem, const Pipe &pp) {
-        double *Vb[2] = {smem, smem + 16 * LDV};
-        double *Tb[2] = {smem + 32 * LDV, smem + 32 * LDV + 256};
+        // buffer x & 1 by arithmetic on smem (not a pointer array) so that
+        // the compiler keeps these LDS addresses and emits LDS instructions
+        auto Vb = [smem](int x) { return smem + (x & 1) * (16 * LDV); };
+        auto Tb = [smem](int x) { return smem + 32 * LDV + (x & 1) * 256; };
         double *Pl = smem + 32 * LDV + 512 + 256;
         const int w = __builtin_amdgcn_readfirstlane(wave_id());
         const bool t0 = threadIdx.x == 0;
-        if (w == 0) geqrt16_panel(Akk, Tkk, Vkk, 0, nullptr, nullptr, Vb[0], Tb[0], Pl);
+        if (w == 0) geqrt16_panel(Akk, Tkk, Vkk, 0, nullptr, nullptr, Vb(0), Tb(0), Pl);
         __syncthreads();
         if (NB == 1 && pp.mine && t0) pipe_publish(pp, 1);
 #pragma unroll 1
         for (int s = 0; s + 1 < NB; ++s) {
-            double *Vs = Vb[s & 1], *Ts = Tb[s & 1];
+            double *Vs = Vb(s & 1), *Ts = Tb(s & 1);
             if (w == 0) {
-                geqrt16_panel(Akk, Tkk, Vkk, s + 1, Vs, Ts, Vb[(s + 1) & 1], Tb[(s + 1) & 1], Pl);
+                geqrt16_panel(Akk, Tkk, Vkk, s + 1, Vs, Ts, Vb((s + 1) & 1), Tb((s + 1) & 1), Pl);
             } else {
                 for (int j = s + 1 + w; j < NB; j += NWAVES - 1) {
                     Strip<B> C;
@@ -628,8 +630,10 @@ struct TileKernels {
     __device__ __forceinline__ static int help_split() { return NB - (5 * NB) / 16; }
 
     __device__ __forceinline__ static void tsqrt16(double *Akk, double *Aik, double *Tik, double *smem, const Pipe &pp) {
-        double *Vb[2] = {smem, smem + 16 * LDV};
-        double *Tb[2] = {smem + 32 * LDV, smem + 32 * LDV + 256};
+        // buffer x & 1 by arithmetic on smem (not a pointer array) so that
+        // the compiler keeps these LDS addresses and emits LDS instructions
+        auto Vb = [smem](int x) { return smem + (x & 1) * (16 * LDV); };
+        auto Tb = [smem](int x) { return smem + 32 * LDV + (x & 1) * 256; };
         double *Rd = smem + 32 * LDV + 512;
         const int w = __builtin_amdgcn_readfirstlane(wave_id());
         const bool t0 = threadIdx.x == 0;
@@ -643,7 +647,7 @@ struct TileKernels {
             __syncthreads();
         }
         if (w == 0) {
-            tsqrt16_panel(Akk, Aik, Tik, 0, nullptr, nullptr, Vb[0], Tb[0], Rd, NB, pp);
+            tsqrt16_panel(Akk, Aik, Tik, 0, nullptr, nullptr, Vb(0), Tb(0), Rd, NB, pp);
         } else if (w == 1 && lane_id() == 0) {
             // while panel 0 is factored, give the helper (released when this
             // task started) a moment to claim its strips; otherwise keep them
@@ -661,9 +665,9 @@ struct TileKernels {
         if (NB == 1 && pp.mine && t0) pipe_publish(pp, 1);
 #pragma unroll 1
         for (int s = 0; s + 1 < NB; ++s) {
-            double *Vs = Vb[s & 1], *Ts = Tb[s & 1];
+            double *Vs = Vb(s & 1), *Ts = Tb(s & 1);
             if (w == 0) {
-                tsqrt16_panel(Akk, Aik, Tik, s + 1, Vs, Ts, Vb[(s + 1) & 1], Tb[(s + 1) & 1], Rd, split, pp);
+                tsqrt16_panel(Akk, Aik, Tik, s + 1, Vs, Ts, Vb((s + 1) & 1), Tb((s + 1) & 1), Rd, split, pp);
             } else {
                 for (int j = s + 1 + w; j < split; j += NWAVES - 1) {
                     Strip<B> C;
@@ -934,7 +938,7 @@ struct TileKernels {
     // (its panel word pp.prev reaches s + 1).
     __device__ __forceinline__ static void apply_dbuf(Strip<B> &C, double *Top, const double *V, const double *T,
                                                       int col0, bool owner, double *smem, const Pipe &pp = Pipe{}) {
-        double *buf[2] = {smem, smem + STAGE_DOUBLES};
+        auto buf = [smem](int x) { return smem + (x & 1) * STAGE_DOUBLES; };
         const bool t0 = threadIdx.x == 0;
         StageRegs R;
         if (TRANS && pp.prev) {
@@ -942,18 +946,18 @@ struct TileKernels {
             __syncthreads();
         }
         stage_fetch(V, T, (TRANS ? 0 : NB - 1) * IB, R);
-        stage_commit(R, buf[0]);
+        stage_commit(R, buf(0));
         __syncthreads();
 #pragma unroll 1
         for (int si = 0; si < NB; ++si) {
             const int c0 = (TRANS ? si : NB - 1 - si) * IB;
-            double *cur = buf[si & 1];
+            double *cur = buf(si & 1);
             d4 Wt[IB / 16];
             if (TS) load_top<B, IB>(Wt, Top + (size_t)col0 * B, c0);
             if (si + 1 < NB) stage_fetch(V, T, (TRANS ? si + 1 : NB - 2 - si) * IB, R);
             panel_update<B, IB, TRANS, TS>(C, TS ? Top + (size_t)col0 * B : nullptr, cur, LDV, cur + (size_t)LDV * IB,
                                            c0, owner, TS ? Wt : nullptr);
-            if (si + 1 < NB) stage_commit(R, buf[(si + 1) & 1]);
+            if (si + 1 < NB) stage_commit(R, buf((si + 1) & 1));
             if (TRANS && pp.prev && t0 && si + 2 < NB) pipe_wait(pp, si + 3);  // block si+2, fetched next
             __syncthreads();
         }
@@ -1038,7 +1042,7 @@ struct TileKernels {
         static_assert(IB == 16, "the FP32 tier works with inner block 16");
         constexpr size_t STAGE_F = (size_t)LDV * IB + IB * IB;
         float *fb = reinterpret_cast<float *>(smem);
-        float *buf[2] = {fb, fb + STAGE_F};
+        auto buf = [fb](int x) { return fb + (x & 1) * STAGE_F; };
         const bool t0 = threadIdx.x == 0;
         StageRegs R;
         if (TRANS && pp.prev) {
@@ -1046,16 +1050,16 @@ struct TileKernels {
             __syncthreads();
         }
         stage_fetch(V, T, (TRANS ? 0 : NB - 1) * IB, R);
-        stage_commit_f(R, buf[0]);
+        stage_commit_f(R, buf(0));
         __syncthreads();
 #pragma unroll 1
         for (int si = 0; si < NB; ++si) {
             const int c0 = (TRANS ? si : NB - 1 - si) * IB;
-            float *cur = buf[si & 1];
+            float *cur = buf(si & 1);
             if (si + 1 < NB) stage_fetch(V, T, (TRANS ? si + 1 : NB - 2 - si) * IB, R);
             panel_update_f32<B, TRANS, TS>(C, TS ? Top + (size_t)col0 * B : nullptr, cur, LDV, cur + (size_t)LDV * IB,
                                            c0, owner);
-            if (si + 1 < NB) stage_commit_f(R, buf[(si + 1) & 1]);
+            if (si + 1 < NB) stage_commit_f(R, buf((si + 1) & 1));
             if (TRANS && pp.prev && t0 && si + 2 < NB) pipe_wait(pp, si + 3);
             __syncthreads();
         }
