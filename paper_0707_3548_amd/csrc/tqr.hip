@@ -912,6 +912,30 @@ struct TileKernels {
             R.t[k] = idx < IB * IB ? T[(size_t)c0 * IB + idx] : 0.0;
         }
     }
+    // Part k (k = 0 .. B/16-1) of stage_fetch: a 16th-of-the-tile share of
+    // V's doubles, and T with part 0; the parts together fetch what
+    // stage_fetch does.
+    __device__ __forceinline__ static void stage_fetch_part(const double *V, const double *T, int c0, StageRegs &R,
+                                                            int k) {
+        static_assert(STAGE_V % (B / 16) == 0 || B / 16 % STAGE_V == 0, "stage parts");
+        constexpr int PER = STAGE_V >= B / 16 ? STAGE_V / (B / 16) : 1;
+        const int tid = threadIdx.x;
+        if (STAGE_V >= B / 16 || k < STAGE_V) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int kk = k * PER + u;
+                const int idx = tid + kk * NT, r = idx % B, c = idx / B;
+                R.v[kk] = V[(size_t)(c0 + c) * B + r];
+            }
+        }
+        if (k == 0) {
+#pragma unroll
+            for (int u = 0; u < STAGE_T; ++u) {
+                const int idx = tid + u * NT;
+                R.t[u] = idx < IB * IB ? T[(size_t)c0 * IB + idx] : 0.0;
+            }
+        }
+    }
     __device__ __forceinline__ static void stage_commit(const StageRegs &R, double *buf) {
         const int tid = threadIdx.x;
         double *Vl = buf, *Tl = buf + (size_t)LDV * IB;
@@ -954,9 +978,13 @@ struct TileKernels {
             double *cur = buf(si & 1);
             d4 Wt[IB / 16];
             if (TS) load_top<B, IB>(Wt, Top + (size_t)col0 * B, c0);
-            if (si + 1 < NB) stage_fetch(V, T, (TRANS ? si + 1 : NB - 2 - si) * IB, R);
+            // the prefetch of block si+1, one part per row block of the
+            // products (after the last block a block is fetched again and
+            // dropped, which keeps the issue free of branches)
+            const int cn = (TRANS ? min(si + 1, NB - 1) : max(NB - 2 - si, 0)) * IB;
+            auto issue = [&](int k) { stage_fetch_part(V, T, cn, R, k); };
             panel_update<B, IB, TRANS, TS>(C, TS ? Top + (size_t)col0 * B : nullptr, cur, LDV, cur + (size_t)LDV * IB,
-                                           c0, owner, TS ? Wt : nullptr);
+                                           c0, owner, TS ? Wt : nullptr, issue);
             if (si + 1 < NB) stage_commit(R, buf((si + 1) & 1));
             if (TRANS && pp.prev && t0 && si + 2 < NB) pipe_wait(pp, si + 3);  // block si+2, fetched next
             __syncthreads();

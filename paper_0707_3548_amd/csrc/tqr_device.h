@@ -148,9 +148,16 @@ __device__ __forceinline__ void load_top(d4 (&W)[IB / 16], const double *top, in
 
 // With `Wtop` the TS form takes the top rows already loaded by load_top
 // (so that their load can be issued ahead of other memory traffic).
-template <int B, int IB, bool TRANS, bool TS>
+// `issue(rb)` is called once per row block rb (0 .. B/16-1) during the V^T C
+// products, so that a caller can spread the issue of its global loads over
+// them instead of stalling the wave's instruction stream with a burst.
+struct NoIssue {
+    __device__ __forceinline__ void operator()(int) const {}
+};
+template <int B, int IB, bool TRANS, bool TS, class Issue = NoIssue>
 __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const double *Vl, int ldv, const double *Tl,
-                                             int c0, bool write_top = true, const d4 *Wtop = nullptr) {
+                                             int c0, bool write_top = true, const d4 *Wtop = nullptr,
+                                             const Issue &issue = Issue{}) {
     constexpr int NA = IB / 16;
     const int l = lane_id();
     const int rb0 = TS ? 0 : c0 / 16;
@@ -163,21 +170,73 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
         if (TS) Wt[a] = Wtop ? Wtop[a] : ld4s(tp + 16 * a, 4);
         W[a] = d4{0.0, 0.0, 0.0, 0.0};
     }
-    // k-slice (rb, r): rows 16rb + 4r + {0..3}; A operand V^T[16a + l%16][16rb + 4r + l/16]
+    // k-slice (rb, r): rows 16rb + 4r + {0..3}; A operand V^T[16a + l%16][16rb + 4r + l/16].
+    // The operands of row block rb+1 are read from LDS before the products of
+    // row block rb are issued (the scheduling fences keep that order): with
+    // one wave per SIMD nothing else hides the LDS latency.
     const double *vp = Vl + (l & 15) * ldv + (l >> 4);
-#pragma unroll
-    for (int rb = 0; rb < B / 16; ++rb) {
-        if (!TS && rb < rb0) continue;
+    auto read_vt = [&](int rb, double (&o)[NA][4]) {
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
             const double *q = vp + 16 * a * ldv + 16 * rb;
-            W[a] = mfma(q[0], C.v[rb].x, W[a]);
-            W[a] = mfma(q[4], C.v[rb].y, W[a]);
-            W[a] = mfma(q[8], C.v[rb].z, W[a]);
-            W[a] = mfma(q[12], C.v[rb].w, W[a]);
+            o[a][0] = q[0];
+            o[a][1] = q[4];
+            o[a][2] = q[8];
+            o[a][3] = q[12];
         }
-        if constexpr (NA > 1) sched_fence();
+    };
+    // op(T) operands of the W2 = op(T) W products, read ahead of them
+    double tv[NA][NA][4];
+#pragma unroll
+    for (int o = 0; o < NA; ++o)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            if (TRANS ? (a > o) : (a < o)) continue;  // T is upper triangular
+            const double *tq = TRANS ? Tl + (16 * o + (l & 15)) * IB + 16 * a + (l >> 4)
+                                     : Tl + (16 * a + (l >> 4)) * IB + 16 * o + (l & 15);
+            const int st = TRANS ? 4 : 4 * IB;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tv[o][a][r] = tq[r * st];
+        }
+    double va[NA][4], vn[NA][4];
+    read_vt(rb0, va);
+#pragma unroll
+    for (int rb = 0; rb < B / 16; ++rb) {
+        if (!TS && rb < rb0) {
+            issue(rb);
+            continue;
+        }
+        if (rb + 1 < B / 16) read_vt(rb + 1, vn);
+        issue(rb);
+        sched_fence();
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            W[a] = mfma(va[a][0], C.v[rb].x, W[a]);
+            W[a] = mfma(va[a][1], C.v[rb].y, W[a]);
+            W[a] = mfma(va[a][2], C.v[rb].z, W[a]);
+            W[a] = mfma(va[a][3], C.v[rb].w, W[a]);
+        }
+        sched_fence();
+        if (rb + 1 < B / 16) {
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) va[a][r] = vn[a][r];
+        }
     }
+    // A operand of the update C -= V W2, k-slice (a, r): V[16rb + l%16][16a + 4r + l/16]
+    const double *vq = Vl + (l >> 4) * ldv + (l & 15);
+    auto read_v = [&](int rb, double (&o)[NA][4]) {
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const double *q = vq + 16 * a * ldv + 16 * rb;
+            o[a][0] = q[0];
+            o[a][1] = q[4 * ldv];
+            o[a][2] = q[8 * ldv];
+            o[a][3] = q[12 * ldv];
+        }
+    };
+    read_v(rb0, va);
     if (TS) {
 #pragma unroll
         for (int a = 0; a < NA; ++a) W[a] += Wt[a];
@@ -189,14 +248,11 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
     for (int o = 0; o < NA; ++o) {
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
-            if (TRANS ? (a > o) : (a < o)) continue;  // T is upper triangular
-            const double *tq = TRANS ? Tl + (16 * o + (l & 15)) * IB + 16 * a + (l >> 4)
-                                     : Tl + (16 * a + (l >> 4)) * IB + 16 * o + (l & 15);
-            const int st = TRANS ? 4 : 4 * IB;
-            W2[o] = mfma(tq[0], W[a].x, W2[o]);
-            W2[o] = mfma(tq[st], W[a].y, W2[o]);
-            W2[o] = mfma(tq[2 * st], W[a].z, W2[o]);
-            W2[o] = mfma(tq[3 * st], W[a].w, W2[o]);
+            if (TRANS ? (a > o) : (a < o)) continue;
+            W2[o] = mfma(tv[o][a][0], W[a].x, W2[o]);
+            W2[o] = mfma(tv[o][a][1], W[a].y, W2[o]);
+            W2[o] = mfma(tv[o][a][2], W[a].z, W2[o]);
+            W2[o] = mfma(tv[o][a][3], W[a].w, W2[o]);
         }
     }
 #pragma unroll
@@ -204,20 +260,26 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
         if (TS && write_top) st4s(tp + 16 * a, 4, Wt[a] - W2[a]);
         W2[a] = -W2[a];
     }
-    // C -= V W2; A operand of k-slice (a, r): V[16rb + l%16][16a + 4r + l/16]
-    const double *vq = Vl + (l >> 4) * ldv + (l & 15);
+    // C -= V W2, with the same one-row-block-ahead operand reads
 #pragma unroll
     for (int rb = 0; rb < B / 16; ++rb) {
         if (!TS && rb < rb0) continue;
+        if (rb + 1 < B / 16) read_v(rb + 1, vn);
+        sched_fence();
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
-            const double *q = vq + 16 * a * ldv + 16 * rb;
-            C.v[rb] = mfma(q[0], W2[a].x, C.v[rb]);
-            C.v[rb] = mfma(q[4 * ldv], W2[a].y, C.v[rb]);
-            C.v[rb] = mfma(q[8 * ldv], W2[a].z, C.v[rb]);
-            C.v[rb] = mfma(q[12 * ldv], W2[a].w, C.v[rb]);
+            C.v[rb] = mfma(va[a][0], W2[a].x, C.v[rb]);
+            C.v[rb] = mfma(va[a][1], W2[a].y, C.v[rb]);
+            C.v[rb] = mfma(va[a][2], W2[a].z, C.v[rb]);
+            C.v[rb] = mfma(va[a][3], W2[a].w, C.v[rb]);
         }
-        if constexpr (NA > 1) sched_fence();
+        sched_fence();
+        if (rb + 1 < B / 16) {
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) va[a][r] = vn[a][r];
+        }
     }
 }
 
