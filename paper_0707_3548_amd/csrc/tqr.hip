@@ -514,26 +514,26 @@ struct TileKernels {
     static constexpr int RPL = B >= 64 ? B / 64 : 1;        // panel rows per lane (one-wave panels)
     static constexpr int PU = 4;                            // column steps unrolled per group in the panels
 
-    // A strip (matrix-core accumulator layout) into LDS as Vl[c * LDV + r].
+    // A strip into LDS as Vl[c * LDV + r].
     __device__ __forceinline__ static void strip_to_lds(const Strip<B> &C, double *Vl) {
         const int l = lane_id();
-        double *p = Vl + (l & 15) * LDV + (l >> 4);
+        double *p = Vl + (l & 15) * LDV + 4 * (l >> 4);
 #pragma unroll
         for (int rb = 0; rb < B / 16; ++rb) {
             p[16 * rb] = C.v[rb].x;
-            p[16 * rb + 4] = C.v[rb].y;
-            p[16 * rb + 8] = C.v[rb].z;
-            p[16 * rb + 12] = C.v[rb].w;
+            p[16 * rb + 1] = C.v[rb].y;
+            p[16 * rb + 2] = C.v[rb].z;
+            p[16 * rb + 3] = C.v[rb].w;
         }
     }
 
     // Row block rb (rows 16rb .. 16rb+15) of a strip to global memory.
     __device__ __forceinline__ static void strip_store_block(const Strip<B> &C, double *col0, int rb) {
         const int l = lane_id();
-        double *p = col0 + (size_t)(l & 15) * B + (l >> 4) + 16 * rb;
+        d4 *p = reinterpret_cast<d4 *>(col0 + (size_t)(l & 15) * B + 4 * (l >> 4) + 16 * rb);
 #pragma unroll
         for (int r = 0; r < B / 16; ++r)
-            if (r == rb) st4s(p, 4, C.v[r]);
+            if (r == rb) *p = C.v[r];
     }
 
     // GEQRT with ib = 16.  Wave 0 factors the panels one after another, each
@@ -1234,7 +1234,7 @@ struct TrsmBody {
                 strip_load<B>(C, Y + (size_t)col0 * B, B);
                 // k-slice (kb, r): rows 16kb + 4r .. +3 of X_j, columns of R
                 const double *xp = X + (size_t)(col0 + (l & 15)) * B + (l >> 4);
-                const double *rp = R + (size_t)(l >> 4) * B + (l & 15);
+                const double *rp = R + (size_t)(l >> 4) * B + strip_row_perm(l & 15);
 #pragma unroll 1
                 for (int kb = 0; kb < B / 16; ++kb) {
                     const d4 x = -ld4s(xp + 16 * kb, 4);
@@ -1297,8 +1297,8 @@ struct TrsmTBody {
     __device__ double *btile(int i) const { return Bt + (int64_t)i * B * wb; }
     __device__ __forceinline__ void run(const Task &t, double *smem) const {
         if (t.kind == 1) {
-            // A operand of k-slice (kb, s): R_ji^T[16rb + l%16][16kb + 4s + l/16]
-            //                              = R_ji[16kb + 4s + l/16][16rb + l%16]
+            // A operand of k-slice (kb, s): R_ji^T[16rb + perm(l%16)][16kb + 4s + l/16]
+            //   = R_ji[16kb + 4s + l/16][16rb + perm(l%16)], perm = strip_row_perm
             const double *R = tile(t.j, t.i);
             const double *X = btile(t.j);
             double *Y = btile(t.i);
@@ -1307,7 +1307,7 @@ struct TrsmTBody {
                 Strip<B> C;
                 strip_load<B>(C, Y + (size_t)col0 * B, B);
                 const double *xp = X + (size_t)(col0 + (l & 15)) * B + (l >> 4);
-                const double *rp = R + (size_t)(l & 15) * B + (l >> 4);
+                const double *rp = R + (size_t)strip_row_perm(l & 15) * B + (l >> 4);
 #pragma unroll 1
                 for (int kb = 0; kb < B / 16; ++kb) {
                     const d4 x = -ld4s(xp + 16 * kb, 4);

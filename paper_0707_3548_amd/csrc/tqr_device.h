@@ -97,32 +97,39 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 }
 
 // ---------------------------------------------------------------------------
-// A 16-column strip of a b-row tile held by one wave in matrix-core
-// accumulator layout: element r of v[rb] holds row 16rb + 4r + l/16 of strip
-// column l%16.  The same registers serve as the B operand of a product that
-// sums over the strip's rows: element r is the k-slice of rows
-// 16rb + 4r .. 16rb + 4r + 3 (lane group l/16 supplies k = l/16).
+// A 16-column strip of a b-row tile held by one wave: element r of v[rb]
+// holds row 16rb + 4(l/16) + r of strip column l%16, four consecutive rows
+// per lane, so that a strip moves to and from memory in 32-byte pieces.
+// As the B operand of a product that sums over the strip's rows, element r
+// of v[rb] is the k-slice of rows {16rb + 4g + r : g = 0..3} (lane group
+// g = l/16 supplies k = g).  As an accumulator, the matrix core returns row
+// 4r + l/16 of its 16-row result in element r; a product whose A operand
+// takes its rows through strip_row_perm lands row 16rb + 4(l/16) + r there.
 // ---------------------------------------------------------------------------
 template <int B>
 struct Strip {
     d4 v[B / 16];
 };
 
+// A-operand row m (0..15) of a product accumulated into a strip's row block
+// reads source row strip_row_perm(m) = 4(m % 4) + m / 4 of that block.
+__device__ __forceinline__ int strip_row_perm(int m) { return 4 * (m & 3) + (m >> 2); }
+
 template <int B>
 __device__ __forceinline__ void strip_load(Strip<B> &s, const double *col0, int ld) {
     const int l = lane_id();
-    const double *p = col0 + (size_t)(l & 15) * ld + (l >> 4);
+    const d4 *p = reinterpret_cast<const d4 *>(col0 + (size_t)(l & 15) * ld + 4 * (l >> 4));
 #pragma unroll
-    for (int rb = 0; rb < B / 16; ++rb) s.v[rb] = ld4s(p + 16 * rb, 4);
+    for (int rb = 0; rb < B / 16; ++rb) s.v[rb] = p[4 * rb];
 }
 
 template <int B>
 __device__ __forceinline__ void strip_store(const Strip<B> &s, double *col0, int ld, int rb0 = 0) {
     const int l = lane_id();
-    double *p = col0 + (size_t)(l & 15) * ld + (l >> 4);
+    d4 *p = reinterpret_cast<d4 *>(col0 + (size_t)(l & 15) * ld + 4 * (l >> 4));
 #pragma unroll
     for (int rb = 0; rb < B / 16; ++rb)
-        if (rb >= rb0) st4s(p + 16 * rb, 4, s.v[rb]);
+        if (rb >= rb0) p[4 * rb] = s.v[rb];
 }
 
 // One wave applies the block reflector of one inner block (IB columns) to its
@@ -170,19 +177,19 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
         if (TS) Wt[a] = Wtop ? Wtop[a] : ld4s(tp + 16 * a, 4);
         W[a] = d4{0.0, 0.0, 0.0, 0.0};
     }
-    // k-slice (rb, r): rows 16rb + 4r + {0..3}; A operand V^T[16a + l%16][16rb + 4r + l/16].
+    // k-slice (rb, r): rows 16rb + 4g + r; A operand V^T[16a + l%16][16rb + 4(l/16) + r].
     // The operands of row block rb+1 are read from LDS before the products of
     // row block rb are issued (the scheduling fences keep that order): with
     // one wave per SIMD nothing else hides the LDS latency.
-    const double *vp = Vl + (l & 15) * ldv + (l >> 4);
+    const double *vp = Vl + (l & 15) * ldv + 4 * (l >> 4);
     auto read_vt = [&](int rb, double (&o)[NA][4]) {
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
             const double *q = vp + 16 * a * ldv + 16 * rb;
             o[a][0] = q[0];
-            o[a][1] = q[4];
-            o[a][2] = q[8];
-            o[a][3] = q[12];
+            o[a][1] = q[1];
+            o[a][2] = q[2];
+            o[a][3] = q[3];
         }
     };
     // op(T) operands of the W2 = op(T) W products, read ahead of them
@@ -224,8 +231,9 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
                 for (int r = 0; r < 4; ++r) va[a][r] = vn[a][r];
         }
     }
-    // A operand of the update C -= V W2, k-slice (a, r): V[16rb + l%16][16a + 4r + l/16]
-    const double *vq = Vl + (l >> 4) * ldv + (l & 15);
+    // A operand of the update C -= V W2, k-slice (a, r):
+    // V[16rb + strip_row_perm(l%16)][16a + 4r + l/16]
+    const double *vq = Vl + (l >> 4) * ldv + strip_row_perm(l & 15);
     auto read_v = [&](int rb, double (&o)[NA][4]) {
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
