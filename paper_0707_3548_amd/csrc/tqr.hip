@@ -135,11 +135,13 @@ __device__ __host__ inline int level_of<TrsmGraph>(const TrsmGraph &, const Task
 // Scheduler words (queue words and slots, dependency counters, the idle
 // bitmap, mailboxes, the done count and the status) are accessed with relaxed
 // system-scope atomics, which no XCD serves from a stale copy in its own L2.
-// Tile data is ordered by explicit fences: a task releases its writes
-// (agent-scope release fence) before it decrements its successors' counters;
-// the worker that finds a task ready acquires the other predecessors' writes
-// and releases them onward (acquire-release fence) before it publishes the
-// task; a worker acquires (agent-scope acquire fence) after it takes a task.
+// Tile data is ordered by explicit fences: a task releases its writes before
+// it decrements its successors' counters (each wave waits for its own stores,
+// then thread 0 issues one agent-scope release, which writes the XCD's L2
+// back), and every task acquires (thread 0, agent-scope acquire: an L2
+// invalidate) before its body runs, wherever it was taken from.  On this
+// chip these cache operations are costly and act on the whole L2, so each
+// task issues exactly one of each.
 #define TQR_FLAG_SCOPE __HIP_MEMORY_SCOPE_SYSTEM
 
 __device__ __forceinline__ uint64_t rt_clock() { return wall_clock64(); }
@@ -488,6 +490,19 @@ __device__ void pipe_publish_on(int32_t *word, int count) {
 }
 __device__ __forceinline__ void pipe_publish(const Pipe &pp, int count) { pipe_publish_on(pp.mine, count); }
 
+// The calling wave waits until its global stores are complete (have reached
+// the L2): s_waitcnt vmcnt(0), with the other counters left alone.
+__device__ __forceinline__ void wait_own_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// A workgroup barrier orders the waves but does not wait for their global
+// stores, and thread 0's release before a publish (an L2 writeback and a
+// wait for its own wave's stores) covers other waves' stores only once they
+// are complete: every other wave waits for its stores before the barrier
+// that precedes such a publish.
+__device__ __forceinline__ void release_before_publish() {
+    if (wave_id() != 0) wait_own_stores();
+}
+
 // ===========================================================================
 // Tile kernels (bodies run by one workgroup)
 // ===========================================================================
@@ -501,7 +516,11 @@ struct TileKernels {
     static constexpr size_t LDS_GENERIC = (PANEL_DOUBLES + 2 * IB * IB + 2 * IB + NWAVES) * sizeof(double);
     // ib = 16 panels: two V buffers (16 x LDV), two T buffers (16 x 16), the
     // 16 x 16 diagonal block of R for TSQRT, the one-wave panel scratch
-    static constexpr size_t LDS_IB16 = (2 * 16 * (size_t)LDV + 2 * 256 + 256 + kPanelScratch) * sizeof(double);
+    // ... and two strip handoff buffers (a strip in the register layout of
+    // Strip<B>: B/16 row blocks of 64 lanes x 4 doubles)
+    static constexpr size_t HAND_OFFSET = 2 * 16 * (size_t)LDV + 2 * 256 + 256 + kPanelScratch;
+    static constexpr size_t HAND_DOUBLES = (size_t)(B / 16) * 256;
+    static constexpr size_t LDS_IB16 = (HAND_OFFSET + 2 * HAND_DOUBLES) * sizeof(double);
     // LARFB/SSRFB with ib = 16 stage V and T of the next inner block while
     // the current one is applied: two buffers of (LDV x 16 + 16 x 16)
     static constexpr size_t STAGE_DOUBLES = (size_t)LDV * IB + IB * IB;
@@ -527,6 +546,24 @@ struct TileKernels {
         }
     }
 
+    // Handoff buffer of strip j (alternating by j).  In block s of GEQRT and
+    // TSQRT the wave that applies the block to strip s+2, the next panel but
+    // one, leaves it here instead of in memory; the lookahead of that panel
+    // in block s+1 takes it from here.
+    __device__ __forceinline__ static double *hand(double *smem, int j) {
+        return smem + HAND_OFFSET + (size_t)(j & 1) * HAND_DOUBLES;
+    }
+    __device__ __forceinline__ static void strip_to_hand(const Strip<B> &C, double *H) {
+        d4 *p = reinterpret_cast<d4 *>(H) + lane_id();
+#pragma unroll
+        for (int rb = 0; rb < B / 16; ++rb) p[64 * rb] = C.v[rb];
+    }
+    __device__ __forceinline__ static void hand_to_strip(Strip<B> &C, const double *H) {
+        const d4 *p = reinterpret_cast<const d4 *>(H) + lane_id();
+#pragma unroll
+        for (int rb = 0; rb < B / 16; ++rb) C.v[rb] = p[64 * rb];
+    }
+
     // Row block rb (rows 16rb .. 16rb+15) of a strip to global memory.
     __device__ __forceinline__ static void strip_store_block(const Strip<B> &C, double *col0, int rb) {
         const int l = lane_id();
@@ -549,22 +586,32 @@ struct TileKernels {
         double *Pl = smem + 32 * LDV + 512 + 256;
         const int w = __builtin_amdgcn_readfirstlane(wave_id());
         const bool t0 = threadIdx.x == 0;
-        if (w == 0) geqrt16_panel(Akk, Tkk, Vkk, 0, nullptr, nullptr, Vb(0), Tb(0), Pl);
+        if (w == 0) geqrt16_panel(Akk, Tkk, Vkk, 0, nullptr, nullptr, Vb(0), Tb(0), Pl, nullptr);
         __syncthreads();
         if (NB == 1 && pp.mine && t0) pipe_publish(pp, 1);
 #pragma unroll 1
         for (int s = 0; s + 1 < NB; ++s) {
             double *Vs = Vb(s & 1), *Ts = Tb(s & 1);
             if (w == 0) {
-                geqrt16_panel(Akk, Tkk, Vkk, s + 1, Vs, Ts, Vb((s + 1) & 1), Tb((s + 1) & 1), Pl);
+                geqrt16_panel(Akk, Tkk, Vkk, s + 1, Vs, Ts, Vb((s + 1) & 1), Tb((s + 1) & 1), Pl,
+                              s + 1 >= 2 ? hand(smem, s + 1) : nullptr);
             } else {
                 for (int j = s + 1 + w; j < NB; j += NWAVES - 1) {
                     Strip<B> C;
                     strip_load<B>(C, Akk + (size_t)16 * j * B, B);
                     panel_update<B, 16, true, false>(C, nullptr, Vs, LDV, Ts, 16 * s);
-                    strip_store<B>(C, Akk + (size_t)16 * j * B, B, s);
+                    if (j == s + 2) {
+                        // the next panel but one: to the handoff buffer, and
+                        // only its final row block s to memory (the panel
+                        // writes the rows below)
+                        strip_to_hand(C, hand(smem, j));
+                        strip_store_block(C, Akk + (size_t)16 * j * B, s);
+                    } else {
+                        strip_store<B>(C, Akk + (size_t)16 * j * B, B, s);
+                    }
                 }
             }
+            if (pp.mine) release_before_publish();
             __syncthreads();
             // row block s is final (and so is row block NB-1 after the last block)
             if (pp.mine && t0) pipe_publish(pp, s + 2 == NB ? NB : s + 1);
@@ -575,13 +622,18 @@ struct TileKernels {
     // block j-1 (Vs, Ts) to it when j > 0; V_j and T_j go to Vn and Tn (LDS)
     // and to Vkk, Tkk and the tile.
     __device__ __forceinline__ static void geqrt16_panel(double *Akk, double *Tkk, double *Vkk, int j, const double *Vs,
-                                                         const double *Ts, double *Vn, double *Tn, double *Pl) {
+                                                         const double *Ts, double *Vn, double *Tn, double *Pl,
+                                                         const double *H) {
         const int l = lane_id();
         const int cj = 16 * j;
         double *colj = Akk + (size_t)cj * B;
         {
             Strip<B> C;
-            strip_load<B>(C, colj, B);
+            // the strip comes from the handoff buffer when one is given
+            if (H)
+                hand_to_strip(C, H);
+            else
+                strip_load<B>(C, colj, B);
             if (j > 0) {
                 panel_update<B, 16, true, false>(C, nullptr, Vs, LDV, Ts, cj - 16);
                 strip_store_block(C, colj, j - 1);  // the R rows of block j-1
@@ -647,7 +699,7 @@ struct TileKernels {
             __syncthreads();
         }
         if (w == 0) {
-            tsqrt16_panel(Akk, Aik, Tik, 0, nullptr, nullptr, Vb(0), Tb(0), Rd, NB, pp);
+            tsqrt16_panel(Akk, Aik, Tik, 0, nullptr, nullptr, Vb(0), Tb(0), Rd, NB, pp, nullptr);
         } else if (w == 1 && lane_id() == 0) {
             // while panel 0 is factored, give the helper (released when this
             // task started) a moment to claim its strips; otherwise keep them
@@ -667,16 +719,23 @@ struct TileKernels {
         for (int s = 0; s + 1 < NB; ++s) {
             double *Vs = Vb(s & 1), *Ts = Tb(s & 1);
             if (w == 0) {
-                tsqrt16_panel(Akk, Aik, Tik, s + 1, Vs, Ts, Vb((s + 1) & 1), Tb((s + 1) & 1), Rd, split, pp);
+                tsqrt16_panel(Akk, Aik, Tik, s + 1, Vs, Ts, Vb((s + 1) & 1), Tb((s + 1) & 1), Rd, split, pp,
+                              s + 1 >= 2 && s + 1 < split ? hand(smem, s + 1) : nullptr);
             } else {
                 for (int j = s + 1 + w; j < split; j += NWAVES - 1) {
                     Strip<B> C;
                     strip_load<B>(C, Aik + (size_t)16 * j * B, B);
                     panel_update<B, 16, true, true>(C, Akk + (size_t)16 * j * B, Vs, LDV, Ts, 16 * s);
-                    strip_store<B>(C, Aik + (size_t)16 * j * B, B);
+                    // the next panel but one goes to the handoff buffer (its
+                    // panel rewrites the whole strip in memory)
+                    if (j == s + 2)
+                        strip_to_hand(C, hand(smem, j));
+                    else
+                        strip_store<B>(C, Aik + (size_t)16 * j * B, B);
                 }
             }
             if (pp.prev && t0) pipe_wait_rows(pp, min(s + 2, NB), NB);
+            if (pp.mine) release_before_publish();
             __syncthreads();
             // this task's part of row block s is final (the helper's part is
             // published by the helper)
@@ -723,6 +782,7 @@ struct TileKernels {
                 panel_update<B, 16, true, true>(C, Akk + (size_t)16 * j * B, Vl, LDV, Tl, 16 * s);
                 strip_store<B>(C, Aik + (size_t)16 * j * B, B);
             }
+            release_before_publish();
             __syncthreads();
             if (t0) pipe_publish_on(pp.hb, s + 1);
         }
@@ -730,25 +790,33 @@ struct TileKernels {
 
     __device__ __forceinline__ static void tsqrt16_panel(double *Akk, double *Aik, double *Tik, int j, const double *Vs,
                                                          const double *Ts, double *Vn, double *Tn, double *Rd, int split,
-                                                         const Pipe &pp) {
+                                                         const Pipe &pp, const double *H) {
         const int l = lane_id();
         const int cj = 16 * j;
         double *acol = Aik + (size_t)cj * B, *rcol = Akk + (size_t)cj * B;
+        // the diagonal block of R (upper triangle), row-major with row r
+        // rotated left by panel_rot(r) (the layout ts_panel16u works in); the
+        // lookahead does not touch it, so its load is issued first
+        double rdv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = l + 64 * q, r = idx >> 4, c = (panel_rot<PU>(r) + (idx & 15)) & 15;
+            rdv[q] = r <= c ? rcol[(size_t)c * B + cj + r] : 0.0;
+        }
         // a helper strip has blocks 0 .. j-2 applied by the helper
         if (j >= split && threadIdx.x == 0) pipe_wait_on(pp, pp.hb, j - 1);
         {
             Strip<B> C;
-            strip_load<B>(C, acol, B);
+            // the strip comes from the handoff buffer when one is given
+            if (H)
+                hand_to_strip(C, H);
+            else
+                strip_load<B>(C, acol, B);
             if (j > 0) panel_update<B, 16, true, true>(C, rcol, Vs, LDV, Ts, cj - 16);
             strip_to_lds(C, Vn);
         }
-        // the diagonal block of R (upper triangle), row-major with row r
-        // rotated left by panel_rot(r) (the layout ts_panel16u works in)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int idx = l + 64 * q, r = idx >> 4, c = (panel_rot<PU>(r) + (idx & 15)) & 15;
-            Rd[idx] = r <= c ? rcol[(size_t)c * B + cj + r] : 0.0;
-        }
+        for (int q = 0; q < 4; ++q) Rd[l + 64 * q] = rdv[q];
         double x[RPL][16];
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
@@ -1411,9 +1479,10 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         if (t < 0) break;
         const int cont = __builtin_amdgcn_readfirstlane(s_cont);
         const uint64_t t_pop = o.trace ? rt_clock() : 0;
-        // a task taken from a queue acquires its predecessors' writes here;
-        // for a continuation the thread that found it ready already did
-        if (!cont) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // acquire the predecessors' writes; the barrier orders every wave's
+        // loads after it
+        if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
         const Task task = g.decode(t);
         if constexpr (std::is_same<G, FactorGraph>::value) {
             // GEQRT(k) starts in order of k: k+1 panels have started
@@ -1428,7 +1497,6 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
             for (int n = 0; n < nearly; ++n) {
                 const int64_t e = g.successor(task, n);
                 if (__hip_atomic_fetch_add(&s.cnt[e], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) == 1) {
-                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
                     push_one(s, level_of(g, g.decode(e), o.policy, flag_load(&s.st->panel)), (int32_t)e);
                     ++pushed;
                 }
@@ -1438,8 +1506,13 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         const uint64_t t_acq = o.trace ? rt_clock() : 0;
         body.run(task, smem);
         const uint64_t t_body = o.trace ? rt_clock() : 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // release the task's writes before its successors are told: every
+        // wave waits for its own stores, then one agent-scope release (an L2
+        // writeback) by thread 0 covers all of them
+        wait_own_stores();
         if (tid == 0) s_panel = flag_load(&s.st->panel);
+        __syncthreads();
+        if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         const int panel = s_panel;
         if (o.trace && tid == 0 && t < o.ntrace) {
@@ -1459,8 +1532,6 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
             const int64_t sidx = g.successor(task, n);
             const int32_t old = __hip_atomic_fetch_add(&s.cnt[sidx], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
             if (old == 1) {
-                // acquire the other predecessors' writes, release them onward
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
                 const int lvl = level_of(g, g.decode(sidx), o.policy, panel);
                 const int slot = atomicAdd(&s_nready, 1);
                 if (slot < kReadyCap) {

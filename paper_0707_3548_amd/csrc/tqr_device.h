@@ -493,6 +493,16 @@ __device__ void panel_t(const double *P, int hp, int ldp, const double *tau, dou
 // column of the compact-WY T, Sec. 2.1).  No workgroup barrier is involved, so
 // the other waves of the workgroup keep updating trailing columns meanwhile.
 // ---------------------------------------------------------------------------
+// Lane `lane`'s v in every lane, through the cross-lane permute (the result
+// stays in vector registers).
+__device__ __forceinline__ double bcast_lane_d(double v, int lane) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_ds_bpermute(lane << 2, w.x);
+    r.y = __builtin_amdgcn_ds_bpermute(lane << 2, w.y);
+    return __builtin_bit_cast(double, r);
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
     const int2 w = __builtin_bit_cast(int2, v);
     int2 r;
@@ -834,51 +844,75 @@ __device__ __forceinline__ void panel_products_add(const double (&x)[RPL][16], c
 
 // T from the Gram columns of an unrolled panel: step j stored column j with
 // the rotation of its group, G(d, j) = Gs[16 j + ((d - rot(j)) & 15)].
+// Row r of T only involves row r (T[r][j] = -tau_j sum_{d<j} T[r][d] G(d, j)
+// for r < j), so lane r keeps its row in registers: no LDS round trip per
+// column, and the same operations in the same order as column by column.
 template <int U>
 __device__ __forceinline__ void panel_t_from_gram_u(const double *Gs, const double *taus, double *Tl) {
     const int l = lane_id(), r = l & 15;
-#pragma unroll 1
+    double t[16];
+#pragma unroll
     for (int j = 0; j < 16; ++j) {
         const double tau = taus[j];
         const int rot = panel_rot<U>(j);
         const double *g = Gs + 16 * j;
         double acc = 0.0;
 #pragma unroll
-        for (int d = 0; d < 15; ++d)
-            if (d < j) acc += Tl[r + 16 * d] * g[(d - rot) & 15];
-        if (l < 16) Tl[l + 16 * j] = l < j ? -tau * acc : (l == j ? tau : 0.0);
+        for (int d = 0; d < j; ++d) acc += t[d] * g[(d - rot) & 15];
+        t[j] = r < j ? -tau * acc : (r == j ? tau : 0.0);
+    }
+    if (l < 16) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) Tl[l + 16 * j] = t[j];
     }
 }
 
 // One step of the unrolled TSQRT panel: step jj = U g + u, pivot in relative
 // column u.  Rr holds the diagonal block of R row-major with row r rotated
 // left by rot(r) (Rr[16 r + c] = R[r][(c + rot(r)) mod 16], zero where that
-// column is left of r).
+// column is left of r).  One batched reduction gives g_c = x_u . x_c over the
+// A rows for every column c: g_u is the sigma^2 of the reflector and, with
+// v = scale x_u, w_c = R[jj][c] + scale g_c (also the Gram column of jj for
+// T, as R row jj is zero in the columns of earlier reflectors).
 template <int RPL, int U, int u>
 __device__ __forceinline__ void ts_step(double (&x)[RPL][16], int g, double *Rr, double *part, double *Gs, double *taus) {
     const int l = lane_id();
     const int jj = U * g + u;
-    double *rrow = Rr + 16 * jj;
-    const double alpha = rrow[u];
-    const double radd = l < 16 ? rrow[l] : 0.0;
-    double s = 0.0;
+    double *rrow = Rr + 16 * jj, *Gcol = Gs + 16 * jj;
+    double rr[16];
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) s = fma(x[i][u], x[i][u], s);
-    const double sigma2 = wave_sum(s);
-    const Reflector h = make_reflector_1div(alpha, sigma2);
+    for (int i = 0; i < 8; ++i) {
+        const double2 t = reinterpret_cast<const double2 *>(rrow)[i];
+        rr[2 * i] = t.x;
+        rr[2 * i + 1] = t.y;
+    }
+    double xu[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) xu[i] = x[i][u];
+    double gm[16], gown;
+    panel_products_add<RPL, -1>(x, xu, 0.0, gm, gown, part, Gcol);
+    const Reflector h = make_reflector_1div(rr[u], gm[u]);
     double v[RPL], tv[RPL];
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
-        v[i] = x[i][u] * h.scale;
+        v[i] = xu[i] * h.scale;
         tv[i] = h.tau * v[i];
     }
-    double P[16], own;
-    panel_products_add<RPL, u>(x, v, radd, P, own, part, Gs + 16 * jj);
+    double P[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) P[c] = fma(h.scale, gm[c], rr[c]);
     // live columns right of the pivot: relative u+1 .. 15 - U g
     const int last = 15 - U * g;
-    if (l < 16) {
-        const bool right = l > u && l <= last;
-        rrow[l] = right ? fma(-h.tau, own, radd) : (l == u ? h.beta : radd);
+    if (l == 0) {
+        double nr[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) nr[c] = c > u && c <= last ? fma(-h.tau, P[c], rr[c]) : (c == u ? h.beta : rr[c]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            reinterpret_cast<double2 *>(Gcol)[i] = double2{P[2 * i], P[2 * i + 1]};
+            reinterpret_cast<double2 *>(rrow)[i] = double2{nr[2 * i], nr[2 * i + 1]};
+        }
+        taus[jj] = h.tau;
     }
 #pragma unroll
     for (int grp = 0; grp < 4; ++grp) {
@@ -893,7 +927,6 @@ __device__ __forceinline__ void ts_step(double (&x)[RPL][16], int g, double *Rr,
             for (int i = 0; i < RPL; ++i) x[i][c] = fma(-P[c], tv[i], x[i][c]);
         }
     }
-    if (l == 0) taus[jj] = h.tau;
 #pragma unroll
     for (int i = 0; i < RPL; ++i) x[i][u] = v[i];
 }
@@ -920,27 +953,40 @@ __device__ __forceinline__ void ts_panel16u(double (&x)[RPL][16], double *Rr, do
     panel_t_from_gram_u<U>(Gs, taus, Tl);
 }
 
+// One step of the unrolled GEQRT panel (pivot: relative row jj of the panel,
+// lane jj of x[0]).  One batched reduction gives g_c = x_u . x_c over the
+// rows below the pivot for every column c: g_u is sigma^2 and, with
+// v = e_jj + scale x_u (below the pivot), w_c = x[jj][c] + scale g_c.
 template <int RPL, int U, int u>
 __device__ __forceinline__ void ge_step(double (&x)[RPL][16], int g, double *part, double *Gs, double *taus) {
     const int l = lane_id();
     const int jj = U * g + u;
     const bool below = l > jj, at = l == jj;
-    double s = 0.0;
+    double pr[16];
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-        const double t = i == 0 && !below ? 0.0 : x[i][u];
-        s = fma(t, t, s);
-    }
-    const double sigma2 = wave_sum(s);
-    const Reflector h = make_reflector_1div(readlane_d(x[0][u], jj), sigma2);
+    for (int c = 0; c < 16; ++c) pr[c] = bcast_lane_d(x[0][c], jj);
+    double xu[RPL];
+    xu[0] = below ? x[0][u] : 0.0;
+#pragma unroll
+    for (int i = 1; i < RPL; ++i) xu[i] = x[i][u];
+    double gm[16], gown;
+    double *Gcol = Gs + 16 * jj;
+    panel_products_add<RPL, -1>(x, xu, 0.0, gm, gown, part, Gcol);
+    const Reflector h = make_reflector_1div(pr[u], gm[u]);
     double v[RPL], tv[RPL];
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
-        v[i] = i == 0 ? (below ? x[0][u] * h.scale : (at ? 1.0 : 0.0)) : x[i][u] * h.scale;
+        v[i] = i == 0 ? (below ? xu[0] * h.scale : (at ? 1.0 : 0.0)) : xu[i] * h.scale;
         tv[i] = h.tau * v[i];
     }
-    double P[16], own;
-    panel_products_add<RPL, u>(x, v, 0.0, P, own, part, Gs + 16 * jj);
+    double P[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) P[c] = fma(h.scale, gm[c], pr[c]);
+    if (l == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) reinterpret_cast<double2 *>(Gcol)[i] = double2{P[2 * i], P[2 * i + 1]};
+        taus[jj] = h.tau;
+    }
     const int last = 15 - U * g;
 #pragma unroll
     for (int grp = 0; grp < 4; ++grp) {
@@ -953,7 +999,6 @@ __device__ __forceinline__ void ge_step(double (&x)[RPL][16], int g, double *par
             for (int i = 0; i < RPL; ++i) x[i][c] = fma(-P[c], tv[i], x[i][c]);
         }
     }
-    if (l == 0) taus[jj] = h.tau;
     x[0][u] = below ? v[0] : (at ? h.beta : x[0][u]);
 #pragma unroll
     for (int i = 1; i < RPL; ++i) x[i][u] = v[i];
