@@ -215,12 +215,16 @@ __device__ int32_t try_pop(const Sched &s, uint64_t deadline, uint32_t &spins, i
     return -1;
 }
 
+// Every level's word is loaded before any is looked at: one memory round
+// trip instead of one per level.
 __device__ __forceinline__ bool queue_has_level_below(const Sched &s, int lvl) {
-    for (int l = 0; l < lvl; ++l) {
-        const uint64_t w = flag_load(&s.st->ht[l]);
-        if ((uint32_t)w < (uint32_t)(w >> 32)) return true;
-    }
-    return false;
+    uint64_t w[kLevels];
+#pragma unroll
+    for (int l = 0; l < kLevels; ++l) w[l] = flag_load(&s.st->ht[l]);
+    bool any = false;
+#pragma unroll
+    for (int l = 0; l < kLevels; ++l) any |= l < lvl && (uint32_t)w[l] < (uint32_t)(w[l] >> 32);
+    return any;
 }
 
 __device__ __forceinline__ void push_one(const Sched &s, int lvl, int32_t t) {
@@ -254,14 +258,26 @@ __device__ int32_t withdraw_idle(const Sched &s, uint64_t *word, uint64_t bit, i
 // worker that releases tasks either hands one over directly (its id) or
 // leaves a wake-up (look at the queues).  A worker that publishes tasks
 // hands them to claimed idle workers or pushes them and then wakes idle
-// workers; with a sequentially consistent fence between the write and the
-// read on both sides (bit set -> queue look; push -> bitmap look), a task
-// published while a worker goes idle is seen by one of the two, so no task is
-// left in a queue while every worker waits.  A sleeping worker also looks at
+// workers; with a store-load fence between the write and the read on both
+// sides (bit set -> queue look; push -> bitmap look), a task published while
+// a worker goes idle is seen by one of the two, so no task is left in a
+// queue while every worker waits.  A sleeping worker also looks at
 // the queues every 64 polls (a queue word can be contended enough that a
 // woken worker loses every exchange for a while).  Waits are bounded by the
 // deadline and a spin count; the periodic check of the done count, the
 // status and the abort flag also ends a wait.
+// Store-load fence for scheduler words: they are accessed only with
+// system-scope atomics, which are performed at memory and never served from
+// an L2, so waiting until this wave's earlier accesses are complete orders
+// them before its later ones (no L2 writeback or invalidate, which an
+// agent-scope fence would issue on the whole XCD's L2).  The signal fences
+// keep the compiler from moving memory accesses across the wait.
+__device__ __forceinline__ void sched_store_load_fence() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 template <class G>
 __device__ int32_t idle_wait(const G &g, int policy, const Sched &s, uint32_t nsinks,
                              const volatile int32_t *abort_flag, uint64_t deadline, int me, int nworkers) {
@@ -275,7 +291,7 @@ __device__ int32_t idle_wait(const G &g, int policy, const Sched &s, uint32_t ns
         if (t >= 0) return t;
         if (t == -2) return -1;
         __hip_atomic_fetch_or(word, bit, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        sched_store_load_fence();
         t = try_pop(s, deadline, spins, nworkers);
         if (t >= 0) {
             const int32_t m = withdraw_idle(s, word, bit, mb, deadline, spins, nworkers);
@@ -329,7 +345,7 @@ __device__ int handoff_ready(const Sched &s, const int32_t *ready, int8_t *lvl, 
     int left = 0;
     for (int r = 0; r < nr; ++r) left += lvl[r] >= 0;
     if (left == 0) return 0;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    sched_store_load_fence();
     int handed = 0, cur_lvl = 0, cur_r = 0;
     // next task in priority order (level, then position); -1 when none left
     auto next_task = [&]() -> int {
@@ -375,7 +391,7 @@ __device__ int handoff_ready(const Sched &s, const int32_t *ready, int8_t *lvl, 
 
 // Thread 0 after pushing `count` tasks: wakes up to `count` idle workers.
 __device__ void wake_idle(const Sched &s, int count, int nworkers) {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    sched_store_load_fence();
     const int nwords = (nworkers + 63) >> 6;
     for (int wi = 0; wi < nwords && count > 0; ++wi) {
         uint64_t v = flag_load(&s.st->idle[wi]);
@@ -1466,7 +1482,6 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
     int32_t next = -1;  // thread 0: continuation task or -1
     for (;;) {
         if (tid == 0) {
-            if (next >= 0 && flag_load(&s.st->status) != 0) next = -1;
             s_cont = next >= 0;
             s_task = next >= 0 ? next
                                : idle_wait(g, o.policy, s, nsinks, o.abort_flag, rt_clock() + (uint64_t)o.timeout,
@@ -1545,6 +1560,9 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         }
         __syncthreads();
         if (tid == 0) {
+            // the status word is read now and looked at only at the end, so
+            // its round trip overlaps the rest
+            const int32_t stat = flag_load(&s.st->status);
             next = -1;
             if (ns == 0) {
                 const uint32_t d = __hip_atomic_fetch_add(&s.st->done, 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) + 1;
@@ -1582,6 +1600,9 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
             }
             if (pushed > 0) wake_idle(s, pushed, nworkers);
             if (best >= 0) next = s_ready[best];
+            // a failed or aborted run takes no continuation (idle_wait sees
+            // the status and ends the worker)
+            if (stat != 0) next = -1;
         }
     }
 }
