@@ -216,11 +216,13 @@ __device__ int32_t try_pop(const Sched &s, uint64_t deadline, uint32_t &spins, i
 }
 
 // Every level's word is loaded before any is looked at: one memory round
-// trip instead of one per level.
-__device__ __forceinline__ bool queue_has_level_below(const Sched &s, int lvl) {
-    uint64_t w[kLevels];
+// trip instead of one per level (read_queue_words), issued early by the
+// caller so that the trip overlaps other waits.
+__device__ __forceinline__ void read_queue_words(const Sched &s, uint64_t (&w)[kLevels]) {
 #pragma unroll
     for (int l = 0; l < kLevels; ++l) w[l] = flag_load(&s.st->ht[l]);
+}
+__device__ __forceinline__ bool queue_has_level_below(const uint64_t (&w)[kLevels], int lvl) {
     bool any = false;
 #pragma unroll
     for (int l = 0; l < kLevels; ++l) any |= l < lvl && (uint32_t)w[l] < (uint32_t)(w[l] >> 32);
@@ -320,7 +322,9 @@ __device__ int32_t idle_wait(const G &g, int policy, const Sched &s, uint32_t ns
                     abort_run(s, nworkers);
                     return -1;
                 }
-                if (queue_has_level_below(s, kLevels)) {
+                uint64_t qw[kLevels];
+                read_queue_words(s, qw);
+                if (queue_has_level_below(qw, kLevels)) {
                     const int32_t m = withdraw_idle(s, word, bit, mb, deadline, spins, nworkers);
                     if (m >= 0) return m;
                     if (m == kMboxStop) return -1;
@@ -1521,6 +1525,14 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         const uint64_t t_acq = o.trace ? rt_clock() : 0;
         body.run(task, smem);
         const uint64_t t_body = o.trace ? rt_clock() : 0;
+        // thread 0 reads the queue words and the status now: the reads
+        // complete during the store wait below
+        uint64_t qw[kLevels];
+        int32_t stat = 0;
+        if (tid == 0) {
+            read_queue_words(s, qw);
+            stat = flag_load(&s.st->status);
+        }
         // release the task's writes before its successors are told: every
         // wave waits for its own stores, then one agent-scope release (an L2
         // writeback) by thread 0 covers all of them
@@ -1560,9 +1572,6 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         }
         __syncthreads();
         if (tid == 0) {
-            // the status word is read now and looked at only at the end, so
-            // its round trip overlaps the rest
-            const int32_t stat = flag_load(&s.st->status);
             next = -1;
             if (ns == 0) {
                 const uint32_t d = __hip_atomic_fetch_add(&s.st->done, 1u, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) + 1;
@@ -1580,7 +1589,7 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
                     best_lvl = lvl;
                 }
             }
-            if (best >= 0 && queue_has_level_below(s, best_lvl)) best = -1;
+            if (best >= 0 && queue_has_level_below(qw, best_lvl)) best = -1;
             // the continuation is not published; the rest go to idle
             // workers first (highest priority first), then to the queues
             if (best >= 0) s_lvl[best] = -1;
