@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_factor_8192_b256.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_0707_3548_amd", "csrc", f) for f in ("tqr.hip", "tqr_device.h", "tqr_graph.h")] + \
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0707_3548_amd", "csrc", f)
+                  for f in ("tqr.hip", "tqr_inst.hip", "tqr_batched.hip", "tqr_impl.h", "tqr_device.h", "tqr_graph.h")] + \
     [os.path.join(ROOT, "paper_0707_3548_amd", "build.py")]
 
 
@@ -43,12 +44,13 @@ def parse():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--tile-b", type=int, default=256)
     ap.add_argument("--inner-ib", type=int, default=16)
-    ap.add_argument("--policy", choices=["paper", "lookahead", "column"], default="column")
+    ap.add_argument("--policy", choices=["default", "paper", "lookahead", "column"], default="default",
+                    help="default: the plain tqr_factor call (no options)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle's CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tall", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--batch-count", type=int, default=20000)
@@ -56,35 +58,72 @@ def parse():
 
 
 def time_factor(tqr, torch, A_host, b, ib, steps, warmup, policy):
-    """Factor `warmup + steps` device copies of A; returns (wall ms/step over
-    the timed steps, the per-step scheduler-launch times from HIP events, the
-    last factored matrix, its workspace)."""
+    """Factor `warmup + steps` device copies of A through the plain boundary
+    call tqr_factor (no options; with --policy other than "default" through
+    tqr_factor_ex with that policy); returns (wall ms/step over the timed
+    steps, the per-step scheduler-launch times from HIP events recorded by the
+    library around the launch in a second pass of the same call with options,
+    the last factored matrix, its workspace)."""
     m, n = A_host.shape
     src = tqr.fortran(torch.from_numpy(A_host).cuda())
     copies = [src.clone() for _ in range(warmup + steps)]  # clone keeps the column-major strides
-    del src
     ws = tqr.Workspace(m, n, 0, b, ib)
-    ev = tqr.HipEvents()
-    evs = [(ev.create(), ev.create()) for _ in range(steps)]
-    pol = {"paper": tqr.POLICY_PAPER, "lookahead": tqr.POLICY_LOOKAHEAD, "column": tqr.POLICY_COLUMN}[policy]
+    pol = {"paper": tqr.POLICY_PAPER, "lookahead": tqr.POLICY_LOOKAHEAD, "column": tqr.POLICY_COLUMN,
+           "default": tqr.POLICY_COLUMN}[policy]
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def run(X, events=None):
+        if policy == "default" and events is None:
+            tqr.factor_plain(X, b, ib, ws)
+        else:
+            tqr.factor(X, b, ib, ws, policy=pol, status=status, events=events)
+
     for w in range(warmup):
-        tqr.factor(copies[w], b, ib, ws, policy=pol, status=status)
+        run(copies[w])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
-        tqr.factor(copies[warmup + s], b, ib, ws, policy=pol, status=status, events=evs[s])
+        run(copies[warmup + s])
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    out = copies[-1].clone()
+    # the scheduler launch alone, from HIP events on the launch stream
+    ev = tqr.HipEvents()
+    evs = [(ev.create(), ev.create()) for _ in range(steps)]
+    for s in range(steps):
+        copies[s].copy_(src)
+    for s in range(steps):
+        run(copies[s], events=evs[s])
+    torch.cuda.synchronize()
     kern_ms = [ev.elapsed_ms(a, e) for a, e in evs]
     if int(status.item()) != 0:
         raise RuntimeError(f"scheduler reported status {int(status.item())}")
     for a, e in evs:
         ev.destroy(a)
         ev.destroy(e)
-    out = copies[-1]
-    del copies[:-1]
+    del copies, src
     return wall_ms, kern_ms, out, ws
+
+
+def cond2_estimate(torch, R, iters=60):
+    """kappa_2 of the input from its R factor (on the device): power
+    iteration on R^T R for sigma_max, inverse iteration through two
+    triangular solves for sigma_min."""
+    g = torch.Generator(device=R.device)
+    g.manual_seed(0)
+    n = R.shape[0]
+    x = torch.randn(n, 1, dtype=torch.float64, device=R.device, generator=g)
+    for _ in range(iters):
+        x = R.T @ (R @ x)
+        x /= torch.linalg.norm(x)
+    smax = float(torch.linalg.norm(R.T @ (R @ x))) ** 0.5
+    y = torch.randn(n, 1, dtype=torch.float64, device=R.device, generator=g)
+    for _ in range(iters):
+        y = torch.linalg.solve_triangular(R, torch.linalg.solve_triangular(R.T, y, upper=False), upper=True)
+        y /= torch.linalg.norm(y)
+    z = torch.linalg.solve_triangular(R, torch.linalg.solve_triangular(R.T, y, upper=False), upper=True)
+    smin = 1.0 / float(torch.linalg.norm(z)) ** 0.5
+    return smax / smin
 
 
 def spot_check(torch, A_host, F, n_check=256):
@@ -139,37 +178,51 @@ def cpu_baseline(A_host, seconds):
                       f"columns of the same 8192x8192 input, standard count 2n^2(m-n/3); {dt:.1f} s"}
 
 
-def serving_leg(count: int):
+def serving_leg(count: int, pool_size: int = 96):
     """The serving loop on the least-squares request stream (m log-uniform in
     [256, 8192], n uniform in [m/8, m], 1-4 right-hand sides, cond
-    log-uniform in [1e1, 1e6], Poisson arrivals): once at the target rate
-    2000 req/s, which saturates one GPU (throughput and queueing latency),
-    once at 10 req/s (latency without queueing).  FP64 answers from the FP64
-    solve; host data pinned before the clock starts, copies in and out
+    log-uniform in [1e1, 1e6], Poisson arrivals): `count` requests at the
+    target rate 2000 req/s, which saturates one GPU (throughput and queueing
+    latency), and a third as many at 100 req/s (below saturation).  The
+    requests' matrices come from a pool of `pool_size` generated requests
+    (arrival i carries pool entry i mod pool_size), so that a thousand
+    requests need neither a thousand host generations nor their pinned
+    memory.  Host data pinned before the clock starts; copies in and out
     timed."""
     from paper_0707_3548_amd import serving, workloads
 
-    out = {"workload": "least-squares requests, m log-uniform [256, 8192], n uniform [m/8, m], 1-4 RHS, "
-                       "cond log-uniform [1e1, 1e6], FP64 solve (factor, Q^T B, back substitution) per request, "
-                       "8 streams, admission by HBM footprint"}
-    for name, rate, seed in (("offered_2000_per_s", 2000.0, 3), ("offered_10_per_s", 10.0, 4)):
-        arr = workloads.arrivals(rate=rate, count=count, seed=seed)
+    out = {"workload": f"least-squares requests, m log-uniform [256, 8192], n uniform [m/8, m], 1-4 RHS, "
+                       f"cond log-uniform [1e1, 1e6], Poisson arrivals, matrices from a pool of {pool_size}; "
+                       "FP64 solve (factor, Q^T B, back substitution) per request, 8 streams, admission by "
+                       "HBM footprint"}
+    pool_spec = workloads.arrivals(rate=1.0, count=pool_size, seed=5)
+    pool = [workloads.ls_request(r["m"], r["n"], r["nrhs"], r["cond"], r["seed"])[:2] for r in pool_spec]
+    for name, rate, cnt, seed in (("offered_2000_per_s", 2000.0, count, 3),
+                                  ("offered_100_per_s", 100.0, max(1, count // 3), 4)):
+        arr = workloads.arrivals(rate=rate, count=cnt, seed=seed)
         ex = serving.GpuExecutor(slots=8)
+        prepared = {}
         reqs = []
         for i, r in enumerate(arr):
-            A, b, _ = workloads.ls_request(r["m"], r["n"], r["nrhs"], r["cond"], r["seed"])
-            reqs.append(ex.prepare(serving.Request(i, r["t"], r["m"], r["n"], r["nrhs"]), A, b))
+            k = i % pool_size
+            A, b = pool[k]
+            if k not in prepared:
+                prepared[k] = ex.prepare(serving.Request(-1, 0.0, A.shape[0], A.shape[1], b.shape[1]), A, b)
+            proto = prepared[k]
+            reqs.append(serving.Request(i, r["t"], proto.m, proto.n, proto.nrhs, proto.footprint,
+                                        ex.payload_copy(proto.payload)))
         sch = serving.Scheduler(8, 64 << 30, ex.launch, ex.poll)
         done = sch.run(reqs)
         st = serving.latency_stats(done)
         span = max(c.t_done for c in done) - min(c.t_arrive for c in done)
         st["gflop_per_s"] = sum(2.0 * r.n * r.n * (r.m - r.n / 3.0) for r in reqs) / span / 1e9
-        bad = sum(int(c.result["info"][0]) != 0 for c in done)
-        out[name] = {k: round(v, 3) for k, v in st.items()} | {"peak_in_flight": sch.peak_inflight,
+        bad = sum(not c.result["ok"] for c in done)
+        out[name] = {k: round(v, 3) for k, v in st.items()} | {"offered_per_s": rate,
+                                                             "peak_in_flight": sch.peak_inflight,
                                                              "peak_hbm_gb": round(sch.peak_bytes / 1e9, 3),
-                                                             "nonzero_info": bad}
-        print(f"bench: serving at {rate:g} req/s: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms",
-              file=sys.stderr, flush=True)
+                                                             "failed": bad}
+        print(f"bench: serving {cnt} requests at {rate:g} req/s: p50 {st['p50_ms']:.1f} ms, "
+              f"p99 {st['p99_ms']:.1f} ms, {st['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
     return out
 
 
@@ -343,6 +396,7 @@ def main():
     achieved_tf = exe / (kern_ms * 1e-3) / 1e12
     print("bench: spot check", file=sys.stderr, flush=True)
     check = spot_check(torch, A, F)
+    check["kappa2_input"] = round(cond2_estimate(torch, torch.triu(F[:n, :])), 1)
     del F, ws
     torch.cuda.empty_cache()
 
@@ -395,9 +449,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"FP64 tiled QR of one {n}x{n} N(0,1) matrix, tile_b={b}, inner_ib={ib}, "
-                               f"persistent task-graph scheduler ({args.policy} priorities"
-                               + (": GEQRT > TSQRT > updates by their column's distance from the current panel)"
-                                  if args.policy == "column" else ")"),
+                               + ("the plain tqr_factor call (persistent task-graph scheduler, default priorities: "
+                                  "GEQRT > TSQRT > updates by their column's distance from the current panel)"
+                                  if args.policy == "default" else
+                                  f"tqr_factor_ex with the {args.policy} priority policy"),
                    "m": n, "n": n, "tile_b": b, "inner_ib": ib},
         "rates": {"gflops_standard_2n2(m-n/3)": round(value, 2),
                   "gflops_tiled_executed": round(exe / (wall_ms * 1e-3) / 1e9, 2),

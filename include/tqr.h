@@ -89,7 +89,8 @@ typedef struct tqr_options {
     int32_t struct_size;       /* sizeof(tqr_options) */
     int32_t workgroups;        /* persistent workers; 0 = one per resident slot */
     int32_t mode;              /* TQR_MODE_PERSISTENT or TQR_MODE_SERIAL */
-    int32_t policy;            /* TQR_POLICY_PAPER (default), TQR_POLICY_LOOKAHEAD or TQR_POLICY_COLUMN */
+    int32_t policy;            /* TQR_POLICY_PAPER, TQR_POLICY_LOOKAHEAD or TQR_POLICY_COLUMN (the
+                                  policy of the calls that take no options) */
     int64_t *trace;            /* device, 8 int64 per task or NULL: taken, acquired,
                                   body done, released (device constant-rate clock
                                   ticks), workgroup, XCD, the wave's

@@ -199,26 +199,28 @@ def orth_error(Q) -> float:
     return float(np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1])))
 
 
-def lstsq(A, B):
+def lstsq(A, B, omp: bool = False):
     """min ||A x - b|| for m >= n and full column rank, via the oracle's QR:
-    x = R_hat^{-1} (Q_hat^T b)[0:n].  Returns (X, info) as trsv_upper."""
+    x = R_hat^{-1} (Q_hat^T b)[0:n].  Returns (X, info) as trsv_upper.
+    ``omp`` runs the factorisation on the OpenMP build (the same bits)."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     if m < n:
         raise ValueError("lstsq needs m >= n")
-    P, tau = geqr2(A)
+    P, tau = geqr2(A, omp=omp)
     C = apply_qt(P, tau, B)
     R = r_factor(P)
     return trsv_upper(R[:n, :n], C[:n])
 
 
-def ls_backward_error(A, x, b) -> float:
+def ls_backward_error(A, x, b, omp: bool = False) -> float:
     """Normwise least-squares backward error estimate (Karlson--Walden):
         eta(x) = ||(A^T A + mu^2 I)^{-1/2} A^T r|| / (||x|| ||A||_F),
         r = b - A x,  mu = ||r|| / ||x||.
     With Rt the R factor of [A; mu I] (= R factor of [R_A; mu I]),
     (A^T A + mu^2 I)^{-1/2} A^T r has the norm of Rt^{-T} A^T r.
-    The R factor is taken from the oracle's own QR."""
+    The R factor is taken from the oracle's own QR (``omp``: its OpenMP
+    build, which gives the same bits)."""
     A = np.asarray(A, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64).reshape(-1)
     b = np.asarray(b, dtype=np.float64).reshape(-1)
@@ -228,10 +230,10 @@ def ls_backward_error(A, x, b) -> float:
     if nx == 0:
         return float(np.linalg.norm(A.T @ r))
     mu = np.linalg.norm(r) / nx
-    P, _ = geqr2(A)
+    P, _ = geqr2(A, omp=omp)
     RA = r_factor(P)[:n, :n]
     aug = np.vstack([RA, mu * np.eye(n)])
-    P2, _ = geqr2(aug)
+    P2, _ = geqr2(aug, omp=omp)
     Rt = r_factor(P2)[:n, :n]
     g = A.T @ r
     # solve Rt^T y = g by forward substitution (Rt^T is lower triangular)

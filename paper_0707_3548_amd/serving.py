@@ -175,11 +175,22 @@ class GpuExecutor:
         Bh.copy_(torch.from_numpy(np.ascontiguousarray(B.T)))
         Xh = torch.empty((nrhs, n), dtype=torch.float64, pin_memory=True)
         info_h = torch.empty(1, dtype=torch.int32, pin_memory=True)
+        status_h = torch.empty(1, dtype=torch.int32, pin_memory=True)
         wb = tqr.workspace_bytes(m, n, nrhs, b, ib)
         te = tqr.t_elems(m, n, b, ib)
         req.footprint = footprint_bytes(m, n, nrhs, b, ib, wb, te)
-        req.payload = {"A": Ah, "B": Bh, "X": Xh, "info": info_h, "tile": (b, ib)}
+        req.payload = {"A": Ah, "B": Bh, "X": Xh, "info": info_h, "status": status_h, "tile": (b, ib)}
         return req
+
+    def payload_copy(self, payload: dict) -> dict:
+        """A payload for another request with the same pinned inputs: its
+        own pinned result buffers, the input buffers shared (they are only
+        read)."""
+        torch = self.torch
+        out = dict(payload)
+        for key in ("X", "info", "status"):
+            out[key] = torch.empty(payload[key].shape, dtype=payload[key].dtype, pin_memory=True)
+        return out
 
     def launch(self, req: Request, slot: int):
         torch, tqr = self.torch, self.tqr
@@ -191,19 +202,25 @@ class GpuExecutor:
             dB = pl["B"].to(self.device, non_blocking=True).t()       # m x nrhs column-major
             ws = tqr.Workspace(req.m, req.n, req.nrhs, b, ib, self.device)
             info = torch.zeros(1, dtype=torch.int32, device=self.device)
+            status = torch.full((1,), -1, dtype=torch.int32, device=self.device)
             w = workers_for(req.m, req.n, b, self.device_slots)
-            tqr.solve_ls(dA, dB, b, ib, ws, workgroups=w, info=info, policy=tqr.POLICY_COLUMN)
+            tqr.solve_ls(dA, dB, b, ib, ws, workgroups=w, info=info, status=status, policy=tqr.POLICY_COLUMN)
             pl["X"].copy_(dB[: req.n].t(), non_blocking=True)
             pl["info"].copy_(info, non_blocking=True)
+            pl["status"].copy_(status, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
         # keep the device tensors alive until the event has passed
-        return {"event": ev, "keep": (dA, dB, ws, info), "payload": pl}
+        return {"event": ev, "keep": (dA, dB, ws, info, status), "payload": pl}
 
     def poll(self, handle):
         """None while the request runs; then {"X": nrhs x n pinned host
-        tensor, "info": the dgels-style info word}."""
+        tensor, "info": the dgels-style info word, "status": the scheduler's
+        status word (0, or TQR_EABORTED when a wait bound or the abort flag
+        ended the solve), "ok": both zero}."""
         if not handle["event"].query():
             return None
         handle["keep"] = None
-        return {"X": handle["payload"]["X"], "info": handle["payload"]["info"]}
+        pl = handle["payload"]
+        ok = int(pl["info"][0]) == 0 and int(pl["status"][0]) == 0
+        return {"X": pl["X"], "info": pl["info"], "status": pl["status"], "ok": ok}

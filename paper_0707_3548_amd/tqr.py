@@ -156,7 +156,7 @@ class Workspace:
 
 
 def factor(A: torch.Tensor, tile_b: int, inner_ib: int, ws: Workspace | None = None, *, workgroups: int = 0,
-           mode: int = MODE_PERSISTENT, policy: int = POLICY_PAPER, trace: torch.Tensor | None = None,
+           mode: int = MODE_PERSISTENT, policy: int = POLICY_COLUMN, trace: torch.Tensor | None = None,
            status: torch.Tensor | None = None, abort_flag=None, timeout_ticks: int = 0,
            events=None, precision: int = PRECISION_FP64):
     """In-place tiled QR of the column-major A; returns (A, T).  ``events`` is
@@ -173,6 +173,20 @@ def factor(A: torch.Tensor, tile_b: int, inner_ib: int, ws: Workspace | None = N
                   events[0] if events else None, events[1] if events else None, precision, 0)
     rc = lib().tqr_factor_ex(m, n, A.data_ptr(), lda, tile_b, inner_ib, ws.T.data_ptr(), ws.work.data_ptr(),
                              ws.work.numel(), _stream(), ctypes.byref(opt))
+    _check("tqr_factor", rc)
+    return A, ws.T
+
+
+def factor_plain(A: torch.Tensor, tile_b: int, inner_ib: int, ws: Workspace | None = None):
+    """In-place tiled QR through the plain boundary call tqr_factor (no
+    options: one persistent launch with the library's default policy);
+    returns (A, T)."""
+    m, n = A.shape
+    lda = _ld(A)
+    if ws is None:
+        ws = Workspace(m, n, 0, tile_b, inner_ib, A.device)
+    rc = lib().tqr_factor(m, n, A.data_ptr(), lda, tile_b, inner_ib, ws.T.data_ptr(), ws.work.data_ptr(),
+                          ws.work.numel(), _stream())
     _check("tqr_factor", rc)
     return A, ws.T
 
@@ -213,7 +227,7 @@ def form_q(A, T, tile_b, inner_ib, Q: torch.Tensor | None = None, ws: Workspace 
 
 
 def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None, *, workgroups: int = 0,
-             status: torch.Tensor | None = None, info: torch.Tensor | None = None, policy: int = POLICY_PAPER):
+             status: torch.Tensor | None = None, info: torch.Tensor | None = None, policy: int = POLICY_COLUMN):
     """min ||A X - B||: A overwritten by its factors, X in B[0:n].  Returns
     (B, info tensor on the device).  ``workgroups`` > 0 caps the persistent
     workers of every phase; ``policy`` picks the priority policy
@@ -224,7 +238,7 @@ def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None, *, workgroups:
         ws = Workspace(m, n, nrhs, tile_b, inner_ib, A.device)
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
-    if workgroups > 0 or status is not None or policy != POLICY_PAPER:
+    if workgroups > 0 or status is not None or policy != POLICY_COLUMN:
         opt = Options(ctypes.sizeof(Options), workgroups, MODE_PERSISTENT, policy, None, None,
                       status.data_ptr() if status is not None else None, 0, None, None)
         rc = lib().tqr_solve_ls_ex(m, n, nrhs, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), tile_b, inner_ib,
@@ -243,7 +257,7 @@ def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None, *, workgroups:
 def solve_ls_mixed(A: torch.Tensor, B: torch.Tensor, tile_b: int, iterations: int = 5, *,
                    precision: int = PRECISION_FP32_UPDATES, workgroups: int = 0, work: torch.Tensor | None = None,
                    X: torch.Tensor | None = None, info: torch.Tensor | None = None, events=None,
-                   policy: int = POLICY_PAPER):
+                   policy: int = POLICY_COLUMN):
     """min ||A X - B|| with the factor's trailing updates in FP32 and FP64
     refinement of the augmented system (tqr_solve_ls_mixed).  A and B are
     column-major and left unchanged; returns (X, T, info)."""

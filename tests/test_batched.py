@@ -140,3 +140,32 @@ def test_batched_graph_replays_match_eager():
         assert torch.equal(bt.A, eager_A), f"replay {rep}: A differs"
         assert torch.equal(bt.T, eager_T), f"replay {rep}: T differs"
         assert int(bt.status.item()) == 0
+
+
+@pytest.mark.gpu
+def test_batched_tuned_table_matches_single_path_and_oracle():
+    """The tile sizes the benchmark uses (autotune.current_table(), b = 128
+    for the widest problems): every problem bitwise the single-problem path
+    with the same tiling, and R against the oracle."""
+    torch = _torch()
+    table = autotune.current_table()
+    shapes = workloads.batch_shapes(160, seed=13) + [(512, 512), (500, 300), (300, 129), (257, 64), (130, 128)]
+    tiles = [autotune.tile_for(n, table) for _, n in shapes]
+    print(f"case batched tuned table {table}: {len(shapes)} problems, tiles {sorted(set(tiles))}", flush=True)
+    mats = workloads.batch_matrices(shapes, seed=14)
+    bt = tqr.Batch(shapes, tiles)
+    bt.load(mats)
+    bt.factor()
+    torch.cuda.synchronize()
+    assert int(bt.status.item()) == 0
+    for i, ((m, n), b) in enumerate(zip(shapes, tiles)):
+        dA = tqr.fortran(torch.from_numpy(mats[i]).cuda())
+        ws = tqr.Workspace(m, n, 0, b, 16)
+        tqr.factor(dA, b, 16, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(bt.matrix(i), dA), f"problem {i} ({m}x{n}, b={b}): factor differs"
+        assert torch.equal(bt.t_slots(i), ws.T[:bt.t_slots(i).numel()]), f"problem {i}: T differs"
+        if i % 5 == 0 or b >= 128:
+            R = np.triu(bt.matrix(i).cpu().numpy()[:n, :])
+            _, R_or = oracle.qr(mats[i])
+            assert oracle.rel_fro(oracle.sign_normalize(R), R_or) < 1e-10, (i, m, n, b)
