@@ -50,6 +50,7 @@ typedef int tqr_status;
 #define TQR_OK 0
 #define TQR_EDEVICE (-1000)   /* a HIP call failed; see tqr_last_error_string() */
 #define TQR_EABORTED (-1001)  /* device-side abort flag or wait time-out (tqr_factor_ex) */
+#define TQR_ESCRATCH (-1002)  /* the problem needs more than the fixed scratch of tqr_factor_noalloc */
 
 /* Number of doubles of the T array for an m x n factorisation: p*q slots of
  * ib x b, p = ceil(m/b), q = ceil(n/b).  Slot (i,k) (0-based tile indices)
@@ -238,6 +239,27 @@ int64_t tqr_batch_plan(int64_t count, tqr_batch_problem *problems);
  * -3 work null, -4 work_bytes below 256, -7 workgroups < 0. */
 tqr_status tqr_factor_batched(int64_t count, const tqr_batch_problem *d_problems, void *work, int64_t work_bytes,
                               int32_t *d_status, int32_t workgroups, hipStream_t stream);
+
+/* ---- Factorisation without a workspace argument ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Exactly
+ * tqr_factor (same kernels, same result bit for bit), with the workspace
+ * taken from a fixed device array inside the library instead of an argument:
+ * TQR_NOALLOC_SCRATCH_BYTES per GPU, set up on the first call on each device
+ * and held until the process ends.  Nothing is allocated or freed in a call
+ * (no hipMalloc, no library allocation); the caller still owns A and T.
+ * Problems whose tqr_workspace_bytes(m, n, 0, tile_b, inner_ib) exceeds the
+ * scratch are rejected with TQR_ESCRATCH before anything is enqueued (for
+ * example 3840 x 3840 at tile_b 256 fits, 4096 x 4096 does not).
+ * Every call on one GPU uses that GPU's single array: calls that overlap in
+ * time on one GPU (different streams, or different host threads without
+ * ordering) race and give undefined results; calls on one stream are
+ * ordered and safe.
+ * Errors: -1 .. -7 as tqr_factor (m, n, A, lda, tile_b, inner_ib, T),
+ * TQR_ESCRATCH, TQR_EDEVICE. */
+#define TQR_NOALLOC_SCRATCH_BYTES (128ll << 20)
+tqr_status tqr_factor_noalloc(int64_t m, int64_t n, double *A, int64_t lda, int tile_b, int inner_ib, double *T,
+                              hipStream_t stream);
 
 /* Description of the last error returned to the calling host thread. */
 const char *tqr_last_error_string(void);

@@ -21,8 +21,9 @@ LIB_PATH = os.path.join(HERE, "libtqr.so")
 
 MODE_PERSISTENT, MODE_SERIAL = 0, 1
 POLICY_PAPER, POLICY_LOOKAHEAD, POLICY_COLUMN = 0, 1, 2
-TQR_EDEVICE, TQR_EABORTED = -1000, -1001
+TQR_EDEVICE, TQR_EABORTED, TQR_ESCRATCH = -1000, -1001, -1002
 PRECISION_FP64, PRECISION_FP32_UPDATES = 0, 1
+NOALLOC_SCRATCH_BYTES = 128 << 20  # TQR_NOALLOC_SCRATCH_BYTES
 
 
 class TqrError(RuntimeError):
@@ -79,6 +80,8 @@ def lib() -> ctypes.CDLL:
         L.tqr_factor.restype = i32
         L.tqr_factor_ex.argtypes = [i64, i64, dp, i64, i32, i32, dp, vp, i64, vp, ctypes.POINTER(Options)]
         L.tqr_factor_ex.restype = i32
+        L.tqr_factor_noalloc.argtypes = [i64, i64, dp, i64, i32, i32, dp, vp]
+        L.tqr_factor_noalloc.restype = i32
         for f in ("tqr_apply_qt", "tqr_apply_q"):
             getattr(L, f).argtypes = [i64, i64, i64, dp, i64, dp, i32, i32, dp, i64, vp, i64, vp]
             getattr(L, f).restype = i32
@@ -189,6 +192,19 @@ def factor_plain(A: torch.Tensor, tile_b: int, inner_ib: int, ws: Workspace | No
                           ws.work.numel(), _stream())
     _check("tqr_factor", rc)
     return A, ws.T
+
+
+def factor_noalloc(A: torch.Tensor, T: torch.Tensor, tile_b: int, inner_ib: int):
+    """In-place tiled QR through tqr_factor_noalloc: the caller passes A and
+    a T of ``t_elems`` doubles; the workspace is the library's fixed scratch
+    (no device allocation in the call)."""
+    m, n = A.shape
+    lda = _ld(A)
+    if T.dtype != torch.float64 or not T.is_cuda or T.numel() < max(t_elems(m, n, tile_b, inner_ib), 0):
+        raise ValueError("T must be a float64 CUDA tensor of at least t_elems(m, n, tile_b, inner_ib) elements")
+    rc = lib().tqr_factor_noalloc(m, n, A.data_ptr(), lda, tile_b, inner_ib, T.data_ptr(), _stream())
+    _check("tqr_factor_noalloc", rc)
+    return A, T
 
 
 def _apply(fn: str, A, T, B, tile_b, inner_ib, ws: Workspace | None):

@@ -103,3 +103,29 @@ def test_solve_ls_ex_option_checks(lib):
     assert lib.tqr_solve_ls_ex(8, 8, 1, fake, 8, fake, 8, 64, 16, fake, fake, big, fake, None, ctypes.byref(serial)) == -15
     # earlier arguments are reported first
     assert lib.tqr_solve_ls_ex(8, 9, 1, fake, 8, fake, 8, 64, 16, fake, fake, big, fake, None, ctypes.byref(bad)) == -1
+
+
+def test_noalloc_argument_checks_and_scratch_limit(lib):
+    """tqr_factor_noalloc validates like tqr_factor and rejects, before any
+    device call, a problem whose workspace exceeds the fixed scratch."""
+    from paper_0707_3548_amd import tqr
+    fake = ctypes.c_void_p(256)  # never dereferenced: validation fails first
+    assert lib.tqr_factor_noalloc(5, 6, fake, 5, 64, 16, fake, None) == -1
+    assert lib.tqr_factor_noalloc(8, 8, None, 8, 64, 16, fake, None) == -3
+    assert lib.tqr_factor_noalloc(8, 8, fake, 4, 64, 16, fake, None) == -4
+    assert lib.tqr_factor_noalloc(8, 8, fake, 8, 48, 16, fake, None) == -5
+    assert lib.tqr_factor_noalloc(8, 8, fake, 8, 64, 24, fake, None) == -6
+    assert lib.tqr_factor_noalloc(8, 8, fake, 8, 64, 16, None, None) == -7
+    assert lib.tqr_factor_noalloc(0, 0, None, 1, 64, 16, None, None) == 0
+    assert lib.tqr_workspace_bytes(3840, 3840, 0, 256, 16) <= tqr.NOALLOC_SCRATCH_BYTES
+    assert lib.tqr_workspace_bytes(4096, 4096, 0, 256, 16) > tqr.NOALLOC_SCRATCH_BYTES
+    assert lib.tqr_factor_noalloc(4096, 4096, fake, 4096, 256, 16, fake, None) == tqr.TQR_ESCRATCH
+    assert b"scratch" in lib.tqr_last_error_string()
+
+
+def test_noalloc_scratch_constant_matches_the_header():
+    src = open(HEADER).read()
+    m = re.search(r"#define TQR_NOALLOC_SCRATCH_BYTES \((\d+)ll << (\d+)\)", src)
+    assert m
+    from paper_0707_3548_amd import tqr
+    assert tqr.NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
