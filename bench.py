@@ -24,7 +24,8 @@ FP64_MFMA_PEAK_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_factor_8192_b256.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0707_3548_amd", "csrc", f)
-                  for f in ("tqr.hip", "tqr_inst.hip", "tqr_batched.hip", "tqr_impl.h", "tqr_device.h", "tqr_graph.h")] + \
+                  for f in ("tqr.hip", "tqr_inst.hip", "tqr_batched.hip", "tqr_impl.h", "tqr_device.h", "tqr_graph.h",
+                            "tqr_narrow.h")] + \
     [os.path.join(ROOT, "paper_0707_3548_amd", "build.py")]
 
 

@@ -146,6 +146,25 @@ __global__ void k_copy_cm(const double *S, int64_t lds, double *D, int64_t ldd, 
     D[c * ldd + r] = S ? scale * S[c * lds + r] : 0.0;
 }
 
+// Column-major blocks of the augmented-system refinement: U = F[0:n] - G and
+// F[0:n] <- G (the vector [h; d2]); rows n.. of F are kept.
+__global__ void k_aug_combine_cm(double *F, int64_t ldf, const double *G, int64_t ldg, double *U, int64_t ldu,
+                                 int64_t n, int nrhs) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nrhs) return;
+    const int64_t r = idx % n, c = idx / n;
+    const double g = G[c * ldg + r];
+    U[c * ldu + r] = F[c * ldf + r] - g;
+    F[c * ldf + r] = g;
+}
+// D += S (rows x nrhs, column-major).
+__global__ void k_add_cm(const double *S, int64_t lds, double *D, int64_t ldd, int64_t rows, int nrhs) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * nrhs) return;
+    const int64_t r = idx % rows, c = idx / rows;
+    D[c * ldd + r] += S[c * lds + r];
+}
+
 __global__ void k_diag_info(const double *W, int p, int b, int64_t n, int32_t *info) {
     __shared__ int32_t best;
     if (threadIdx.x == 0) best = 0x7fffffff;
@@ -287,6 +306,13 @@ static tqr_status apply_common(bool trans, int64_t m, int64_t n, int64_t nrhs, c
     hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, A, lda, m, n, W,
                        (int)z.p, tile_b, tile_b);
     hipLaunchKernelGGL(k_unit_lower, dim3((unsigned)std::min(z.p, z.q)), dim3(256), 0, stream, W, (int)z.p, tile_b, Vd);
+    if (narrow_ok(tile_b, inner_ib, nrhs)) {
+        // in place on B, one workgroup per row tile (no B tiles)
+        const NarrowMem nm = narrow_mem(work, z, tile_b);
+        return dispatch(tile_b, inner_ib, [&](const PairFns &f) {
+            return f.apply_narrow(trans, m, n, nrhs, T, W, Vd, B, ldb, nm, stream, nullptr);
+        });
+    }
     tqr_status st = dispatch(tile_b, inner_ib, [&](const PairFns &f) {
         return f.apply(trans, m, n, nrhs, T, W, Vd, B, ldb, Bt, sched, stream, nullptr);
     });

@@ -1625,6 +1625,9 @@ __global__ void k_aug_combine(double *Dt, const double *Ht, double *Ut, int b, i
 __global__ void k_tiles_add_to_cm(const double *Bt, int b, int wb, double *Y, int64_t rows, int nrhs);
 __global__ void k_copy_cm(const double *S, int64_t lds, double *D, int64_t ldd, int64_t rows, int nrhs, double scale);
 __global__ void k_diag_info(const double *W, int p, int b, int64_t n, int32_t *info);
+__global__ void k_aug_combine_cm(double *F, int64_t ldf, const double *G, int64_t ldg, double *U, int64_t ldu,
+                                 int64_t n, int nrhs);
+__global__ void k_add_cm(const double *S, int64_t lds, double *D, int64_t ldd, int64_t rows, int nrhs);
 
 // ===========================================================================
 // Host side
@@ -1654,11 +1657,21 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 inline int64_t wb_of(int64_t nrhs) { return cdiv(std::max<int64_t>(nrhs, 1), 16) * 16; }
 
+#include "tqr_narrow.h"
+
+inline bool narrow_ok(int b, int ib, int64_t nrhs) { return ib == 16 && b >= 64 && nrhs >= 1 && nrhs <= kNarrowRhs; }
+
 // Workspace: [tiles p*q*b*b][dense diagonal V q*b*b][B tiles p*b*wb][scheduler]
-// [R_kk chain progress words p*q int32]
+// [R_kk chain progress words p*q int32][narrow-rhs words and hand-over blocks]
+// The narrow region (only when narrow_ok): 64 control ints (apply: ticket,
+// abort at 0, 1; triangular solves: at 2, 3), the apply flags (q*p*b/16),
+// the solve flags (one per 64-row block), then the apply hand-over blocks
+// (q*p*b*kNarrowRhs doubles) and the published solution blocks.
 struct Sizes {
     int64_t p, q, tiles_bytes, vd_bytes, btiles_bytes, sched_bytes, prog_bytes, total;
+    int64_t nar_ints, nar_h_bytes, nar_x_bytes, nar_bytes;
     int64_t prog_offset() const { return tiles_bytes + vd_bytes + btiles_bytes + sched_bytes; }
+    int64_t narrow_offset() const { return prog_offset() + prog_bytes; }
 };
 
 inline Sizes sizes_of(int64_t m, int64_t n, int64_t nrhs, int b) {
@@ -1676,8 +1689,32 @@ inline Sizes sizes_of(int64_t m, int64_t n, int64_t nrhs, int b) {
     }
     z.sched_bytes = align256(sched_bytes(nt));
     z.prog_bytes = align256(4 * z.p * z.q * 4);
-    z.total = z.tiles_bytes + z.vd_bytes + z.btiles_bytes + z.sched_bytes + z.prog_bytes;
+    z.nar_ints = z.nar_h_bytes = z.nar_x_bytes = z.nar_bytes = 0;
+    if (nrhs >= 1 && nrhs <= kNarrowRhs && b >= 64) {
+        const int64_t nb = cdiv(std::max<int64_t>(n, 1), kTrsvRows);
+        z.nar_ints = 64 + z.q * z.p * (b / 16) + nb;
+        z.nar_h_bytes = align256(z.q * z.p * (int64_t)b * kNarrowRhs * 8);
+        z.nar_x_bytes = align256(nb * kTrsvRows * kNarrowRhs * 8);
+        z.nar_bytes = align256(z.nar_ints * 4) + z.nar_h_bytes + z.nar_x_bytes;
+    }
+    z.total = z.tiles_bytes + z.vd_bytes + z.btiles_bytes + z.sched_bytes + z.prog_bytes + z.nar_bytes;
     return z;
+}
+
+// Pointers into the narrow region of a workspace laid out by sizes_of.
+struct NarrowMem {
+    int32_t *ints, *apply_flags, *trsv_flags;
+    double *H, *X;
+};
+inline NarrowMem narrow_mem(void *work, const Sizes &z, int b) {
+    char *base = reinterpret_cast<char *>(work) + z.narrow_offset();
+    NarrowMem nm;
+    nm.ints = reinterpret_cast<int32_t *>(base);
+    nm.apply_flags = nm.ints + 64;
+    nm.trsv_flags = nm.apply_flags + z.q * z.p * (b / 16);
+    nm.H = reinterpret_cast<double *>(base + align256(z.nar_ints * 4));
+    nm.X = reinterpret_cast<double *>(base + align256(z.nar_ints * 4) + z.nar_h_bytes);
+    return nm;
 }
 
 // Two seconds of the device's constant-rate clock: a worker that finds no
@@ -1864,6 +1901,90 @@ tqr_status trsmt_impl(int64_t m, int64_t n, int64_t nrhs, const double *W, doubl
                      opt ? opt->status : nullptr, 1);
 }
 
+// ---- narrow right-hand sides (tqr_narrow.h) --------------------------------
+// Q^T B (trans) or Q B in place on the column-major m x nrhs block Bm
+// (1 <= nrhs <= kNarrowRhs), one workgroup per row tile.  Control words and
+// flags are cleared on the stream first (a fill kernel, no memset).
+template <int B, int IB>
+tqr_status narrow_apply(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *T, const double *W,
+                        const double *Vd, double *Bm, int64_t ldb, const NarrowMem &nm, hipStream_t stream,
+                        const tqr_options *opt) {
+    if constexpr (IB != 16 || B < 64) {
+        return set_err(TQR_EDEVICE, "narrow application needs inner_ib 16 and tile_b >= 64");
+    } else {
+        const int64_t p = cdiv(m, B), q = cdiv(n, B);
+        const int64_t nflags = q * p * (B / 16);
+        hipLaunchKernelGGL(k_fill_int, dim3((unsigned)cdiv(64 + nflags, 256)), dim3(256), 0, stream, nm.ints,
+                           64 + nflags, 0);
+        NarrowApplyArgs a;
+        a.W = W;
+        a.Vd = Vd;
+        a.T = T;
+        a.Bm = Bm;
+        a.ldb = ldb;
+        a.m = m;
+        a.nrhs = (int)nrhs;
+        a.p = (int)p;
+        a.q = (int)q;
+        a.H = nm.H;
+        a.flags = nm.apply_flags;
+        a.ctl.ticket = nm.ints;
+        a.ctl.abort = nm.ints + 1;
+        a.ctl.status = opt ? opt->status : nullptr;
+        a.ctl.timeout = (opt && opt->timeout_ticks > 0) ? opt->timeout_ticks : default_timeout_ticks();
+        const dim3 grid((unsigned)p), block(B);
+        if (nrhs == 1) {
+            if (trans) hipLaunchKernelGGL((k_narrow_apply<B, IB, 1, true>), grid, block, 0, stream, a);
+            else hipLaunchKernelGGL((k_narrow_apply<B, IB, 1, false>), grid, block, 0, stream, a);
+        } else if (nrhs == 2) {
+            if (trans) hipLaunchKernelGGL((k_narrow_apply<B, IB, 2, true>), grid, block, 0, stream, a);
+            else hipLaunchKernelGGL((k_narrow_apply<B, IB, 2, false>), grid, block, 0, stream, a);
+        } else {
+            if (trans) hipLaunchKernelGGL((k_narrow_apply<B, IB, 4, true>), grid, block, 0, stream, a);
+            else hipLaunchKernelGGL((k_narrow_apply<B, IB, 4, false>), grid, block, 0, stream, a);
+        }
+        HIPCHK(hipGetLastError());
+        return TQR_OK;
+    }
+}
+
+// R X = Y (trans false) or R^T X = Y (trans true) in place on the
+// column-major n x nrhs block Y, R the upper triangle of the tiles W.
+template <int B>
+tqr_status narrow_trsv(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *W, double *Y, int64_t ldy,
+                       const NarrowMem &nm, hipStream_t stream, const tqr_options *opt) {
+    const int64_t p = cdiv(m, B);
+    const int64_t nb = cdiv(n, kTrsvRows);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, stream, nm.ints + 2, (int64_t)2, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)cdiv(nb, 256)), dim3(256), 0, stream, nm.trsv_flags, nb, 0);
+    NarrowTrsvArgs a;
+    a.W = W;
+    a.p = (int)p;
+    a.n = n;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.nrhs = (int)nrhs;
+    a.X = nm.X;
+    a.flags = nm.trsv_flags;
+    a.ctl.ticket = nm.ints + 2;
+    a.ctl.abort = nm.ints + 3;
+    a.ctl.status = opt ? opt->status : nullptr;
+    a.ctl.timeout = (opt && opt->timeout_ticks > 0) ? opt->timeout_ticks : default_timeout_ticks();
+    const dim3 grid((unsigned)nb), block(256);
+    if (nrhs == 1) {
+        if (trans) hipLaunchKernelGGL((k_narrow_trsv<B, 1, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_narrow_trsv<B, 1, false>), grid, block, 0, stream, a);
+    } else if (nrhs == 2) {
+        if (trans) hipLaunchKernelGGL((k_narrow_trsv<B, 2, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_narrow_trsv<B, 2, false>), grid, block, 0, stream, a);
+    } else {
+        if (trans) hipLaunchKernelGGL((k_narrow_trsv<B, 4, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_narrow_trsv<B, 4, false>), grid, block, 0, stream, a);
+    }
+    HIPCHK(hipGetLastError());
+    return TQR_OK;
+}
+
 inline tqr_status check_opts(const tqr_options *o) {
     if (!o) return TQR_OK;
     if (o->struct_size != (int32_t)sizeof(tqr_options)) return -11;
@@ -1896,6 +2017,15 @@ tqr_status solve_impl(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda
     hipLaunchKernelGGL(k_tiles_to_cm, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, W, (int)z.p, B, B, A,
                        lda, m, n);
     if (nrhs == 0) return TQR_OK;
+    if (narrow_ok(B, IB, nrhs)) {
+        // Q^T B and the back substitution in place on B, one workgroup per
+        // row tile / row block (tqr_narrow.h)
+        const NarrowMem nm = narrow_mem(work, z, B);
+        s1 = narrow_apply<B, IB>(true, m, n, nrhs, T, W, Vd, Bm, ldb, nm, stream, po);
+        if (s1 != TQR_OK) return s1;
+        hipLaunchKernelGGL(k_diag_info, dim3(1), dim3(256), 0, stream, W, (int)z.p, B, n, d_info);
+        return narrow_trsv<B>(false, m, n, nrhs, W, Bm, ldb, nm, stream, po);
+    }
     s1 = apply_impl<B, IB>(true, m, n, nrhs, T, W, Vd, Bm, ldb, Bt, sched, stream, po);
     if (s1 != TQR_OK) return s1;
     hipLaunchKernelGGL(k_diag_info, dim3(1), dim3(256), 0, stream, W, (int)z.p, B, n, d_info);
@@ -1965,6 +2095,33 @@ tqr_status mixed_impl(int64_t m, int64_t n, int64_t nrhs, const double *A, int64
     hipLaunchKernelGGL(k_diag_info, dim3(1), dim3(256), 0, stream, W, (int)z.p, B, n, d_info);
     hipLaunchKernelGGL(k_copy_cm, dim3(gn), dim3(256), 0, stream, nullptr, 0, Xv, n, n, (int)nrhs, 0.0);
     hipLaunchKernelGGL(k_copy_cm, dim3(gm), dim3(256), 0, stream, Bm, ldb, Rv, m, m, (int)nrhs, 1.0);
+    if (narrow_ok(B, 16, nrhs)) {
+        // the same refinement with the narrow kernels: F, G and U (= Ut as an
+        // n x nrhs column-major block) are worked on in place
+        const NarrowMem nm = narrow_mem(work, z, B);
+        for (int it = 0; it < iterations; ++it) {
+            hipLaunchKernelGGL(k_resid_partial, dim3((unsigned)cdiv(m, 256), kResidChunks), dim3(256), 0, stream, A,
+                               lda, m, n, Xv, n, (int)nrhs, Part);
+            hipLaunchKernelGGL(k_resid_reduce, dim3(gm), dim3(256), 0, stream, Bm, ldb, Rv, m, (int)nrhs, kResidChunks,
+                               Part, F);
+            hipLaunchKernelGGL(k_neg_atr, dim3((unsigned)n), dim3(NT), 0, stream, A, lda, m, Rv, (int)nrhs, G, n);
+            s1 = narrow_apply<B, 16>(true, m, n, nrhs, T, W, Vd, F, m, nm, stream, &o);  // d = Q^T f
+            if (s1 != TQR_OK) return s1;
+            s1 = narrow_trsv<B>(true, m, n, nrhs, W, G, n, nm, stream, &o);  // h = R^{-T} g
+            if (s1 != TQR_OK) return s1;
+            // u = d[0:n] - h;  f <- [h; d[n:m]]
+            hipLaunchKernelGGL(k_aug_combine_cm, dim3(gn), dim3(256), 0, stream, F, m, G, n, Ut, n, n, (int)nrhs);
+            s1 = narrow_trsv<B>(false, m, n, nrhs, W, Ut, n, nm, stream, &o);  // dx = R^{-1} u
+            if (s1 != TQR_OK) return s1;
+            s1 = narrow_apply<B, 16>(false, m, n, nrhs, T, W, Vd, F, m, nm, stream, &o);  // dr = Q [h; d2]
+            if (s1 != TQR_OK) return s1;
+            hipLaunchKernelGGL(k_add_cm, dim3(gn), dim3(256), 0, stream, Ut, n, Xv, n, n, (int)nrhs);
+            hipLaunchKernelGGL(k_add_cm, dim3(gm), dim3(256), 0, stream, F, m, Rv, m, m, (int)nrhs);
+        }
+        hipLaunchKernelGGL(k_copy_cm, dim3(gn), dim3(256), 0, stream, Xv, n, X, ldx, n, (int)nrhs, 1.0);
+        HIPCHK(hipGetLastError());
+        return TQR_OK;
+    }
     for (int it = 0; it < iterations; ++it) {
         // FP64 residuals of the augmented system
         hipLaunchKernelGGL(k_resid_partial, dim3((unsigned)cdiv(m, 256), kResidChunks), dim3(256), 0, stream, A, lda, m,
@@ -2004,6 +2161,11 @@ struct PairFns {
                         double *Bm, int64_t ldb, double *Bt, void *sched, hipStream_t stream, const tqr_options *opt);
     tqr_status (*solve)(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *Bm, int64_t ldb, double *T,
                         void *work, int32_t *d_info, hipStream_t stream, const tqr_options *po);
+    // Q^T / Q on a narrow column-major block (inner block 16 and tile_b 64,
+    // 128 or 256 only; null otherwise)
+    tqr_status (*apply_narrow)(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *T, const double *W,
+                               const double *Vd, double *Bm, int64_t ldb, const NarrowMem &nm, hipStream_t stream,
+                               const tqr_options *opt);
     // inner block 16 and tile_b 64, 128 or 256 only; null otherwise
     tqr_status (*mixed)(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *Bm, int64_t ldb,
                         double *X, int64_t ldx, int iterations, double *T, void *work, int32_t *d_info,

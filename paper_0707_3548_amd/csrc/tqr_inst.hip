@@ -15,7 +15,10 @@ static PairFns make_pair_fns() {
     f.factor = &factor_impl<B, IB>;
     f.apply = &apply_impl<B, IB>;
     f.solve = &solve_impl<B, IB>;
-    if constexpr (IB == 16 && B >= 64) f.mixed = &mixed_impl<B>;
+    if constexpr (IB == 16 && B >= 64) {
+        f.mixed = &mixed_impl<B>;
+        f.apply_narrow = &narrow_apply<B, IB>;
+    }
     return f;
 }
 
