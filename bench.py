@@ -230,10 +230,10 @@ def serving_leg(count: int, pool_size: int = 96):
 def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
     """The FP32 precision tier: (1) the same 8192x8192 factorisation with the
     trailing updates on the FP32 matrix cores (FP64 panels), timed like the
-    headline; (2) least squares 16384x4096 (A = U diag(s) V^T, cond 1e5,
-    one right-hand side) solved in FP64 and mixed (FP32-update factor + 5
-    FP64 refinement steps), both with inputs in HBM, and the relative
-    difference of the two solutions."""
+    headline; (2) least squares 16384x4096 at cond 1e2, 1e5 and 1e8, solved
+    in FP64 and mixed (FP32-update factor, or the FP64 factor, + FP64 CGLS),
+    inputs in HBM: times, iterations, the device's backward-error estimate,
+    and the relative difference from the FP64 solution."""
     import numpy as np
     import torch
     from paper_0707_3548_amd import tqr, workloads
@@ -262,10 +262,13 @@ def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
     del copies, ws, src
     torch.cuda.empty_cache()
 
-    lm, ln, cond = 16384, 4096, 1e5
-    Ah, Bh, _ = workloads.ls_request(lm, ln, 1, cond, seed=41)
-    dA0 = tqr.fortran(torch.from_numpy(Ah).cuda())
-    dB0 = tqr.fortran(torch.from_numpy(Bh).cuda())
+    # least squares 16384 x 4096 (A = U diag(s) V^T, U and V from QR of
+    # Gaussians, s log-spaced; b = A x + 1e-6 N(0,1)) per condition number:
+    # the FP64 solve (factor, Q^T b, back substitution) against the mixed
+    # solve (FP32-update factor + FP64 CGLS on A R^{-1}, stopping on the
+    # device), and the mixed solve with the FP64 factor where cond exceeds
+    # 1 / u32 (the FP32 factor stalls there and says so in its statistics)
+    lm, ln = 16384, 4096
     work = torch.empty(int(tqr.lib().tqr_ls_mixed_workspace_bytes(lm, ln, 1, 256)), dtype=torch.uint8, device="cuda")
     ws64 = tqr.Workspace(lm, ln, 1, 256, 16)
 
@@ -278,30 +281,48 @@ def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
             t.append(e0.elapsed_time(e1))
         return sorted(t[1:])[len(t[1:]) // 2]
 
-    def run64(e0, e1):
-        dA, dB = dA0.clone(), dB0.clone()
-        e0.record()
-        tqr.solve_ls(dA, dB, 256, 16, ws64, policy=tqr.POLICY_COLUMN)
-        e1.record()
-        run64.X = dB
+    ls = {"workload": f"{lm}x{ln} least squares, A = U diag(s) V^T (U, V from QR of Gaussians, s log-spaced), "
+                      "one right-hand side b = A x + 1e-6 N(0,1); FP64 solve vs FP32-update factor + FP64 CGLS "
+                      "(at most 20 iterations, device stopping test)"}
+    for cond in (1e2, 1e5, 1e8):
+        Ah, Bh, _ = workloads.ls_problem(lm, ln, cond, seed=41, nrhs=1)
+        dA0 = tqr.fortran(torch.from_numpy(Ah).cuda())
+        dB0 = tqr.fortran(torch.from_numpy(Bh).cuda())
+        del Ah
 
-    def runmx(e0, e1):
-        e0.record()
-        X, _, info = tqr.solve_ls_mixed(dA0, dB0, 256, iterations=5, work=work, policy=tqr.POLICY_COLUMN)
-        e1.record()
-        runmx.X, runmx.info = X, info
+        def run64(e0, e1):
+            dA, dB = dA0.clone(), dB0.clone()
+            e0.record()
+            tqr.solve_ls(dA, dB, 256, 16, ws64)
+            e1.record()
+            run64.X = dB
 
-    t64 = time_it(run64)
-    tmx = time_it(runmx)
-    x64 = run64.X[:ln].cpu().numpy()
-    xmx = runmx.X.cpu().numpy()
-    out["least_squares"] = {"workload": f"{lm}x{ln}, A = U diag(s) V^T with cond {cond:g}, one right-hand side, "
-                                        "b = A x + 1e-6 noise", "fp64_ms": round(t64, 3), "mixed_ms": round(tmx, 3),
-                            "mixed_iterations": 5, "speedup": round(t64 / tmx, 3),
-                            "rel_diff_mixed_vs_fp64": float(np.linalg.norm(xmx - x64) / np.linalg.norm(x64)),
-                            "info": int(runmx.info.item())}
-    print(f"bench: mixed tier: factor {ms:.2f} ms (fp64 {fp64_ms:.2f}); LS fp64 {t64:.2f} ms, mixed {tmx:.2f} ms",
-          file=sys.stderr, flush=True)
+        def runmx(e0, e1, prec):
+            e0.record()
+            X, _, info, stats = tqr.solve_ls_mixed(dA0, dB0, 256, iterations=20, work=work, precision=prec)
+            e1.record()
+            runmx.X, runmx.info, runmx.stats = X, info, stats
+
+        t64 = time_it(run64)
+        x64 = run64.X[:ln].cpu().numpy()
+        row = {"fp64_ms": round(t64, 3)}
+        for name, prec in (("fp32_factor", tqr.PRECISION_FP32_UPDATES), ("fp64_factor", tqr.PRECISION_FP64)):
+            tmx = time_it(lambda e0, e1: runmx(e0, e1, prec))
+            st = tqr.refine_stats(runmx.stats)[0]
+            xmx = runmx.X.cpu().numpy()
+            row[name] = {"ms": round(tmx, 3), "speedup_vs_fp64": round(t64 / tmx, 3), "iterations": st["iterations"],
+                         "stop": {1: "converged", 2: "stagnated", 3: "iteration limit", 4: "breakdown"}.get(st["stop"], st["stop"]),
+                         "eta_estimate": st["eta"],
+                         "rel_diff_vs_fp64_solution": float(np.linalg.norm(xmx - x64) / np.linalg.norm(x64)),
+                         "info": int(runmx.info.item())}
+        ls[f"cond_{cond:g}"] = row
+        print(f"bench: LS cond {cond:g}: fp64 {t64:.2f} ms, mixed fp32 {row['fp32_factor']['ms']:.2f} ms "
+              f"({row['fp32_factor']['iterations']} it, {row['fp32_factor']['stop']}, eta {row['fp32_factor']['eta_estimate']:.2e}), "
+              f"mixed fp64-factor {row['fp64_factor']['ms']:.2f} ms", file=sys.stderr, flush=True)
+        del dA0, dB0
+        torch.cuda.empty_cache()
+    out["least_squares"] = ls
+    print(f"bench: mixed tier: factor {ms:.2f} ms (fp64 {fp64_ms:.2f})", file=sys.stderr, flush=True)
     return out
 
 

@@ -184,27 +184,50 @@ tqr_status tqr_solve_ls_ex(int64_t m, int64_t n, int64_t nrhs, double *A, int64_
                            int32_t *d_info, hipStream_t stream, const tqr_options *options);
 
 /* ---- Mixed-precision least squares with FP64 refinement ----
- * min ||A X - B||_F for m >= n.  A copy of A is factorised with the trailing
- * updates on the FP32 matrix cores (TQR_PRECISION_FP32_UPDATES; options may
- * ask for TQR_PRECISION_FP64 instead), then `iterations` steps of iterative
- * refinement of the augmented system [I A; A^T 0][r; x] = [B; 0] (Bjorck)
- * run with FP64 residuals: f = B - r - A x, g = -A^T r (FP64 kernels on the
- * caller's A), the correction from the factor (h = R^{-T} g,
- * d = Q^T f, dx = R^{-1}(d[0:n] - h), dr = Q [h; d[n:m]]), x += dx, r += dr,
- * starting from x = 0, r = B.  Each step reduces the error by about
- * cond(A) times the factor's relative accuracy.  A and B are not modified.
- *   X      : device, n x nrhs column-major (ldx >= max(1, n)), written.
- *   T      : device, tqr_t_elems(m, n, tile_b, 16) doubles, written.
- *   work   : tqr_ls_mixed_workspace_bytes(m, n, nrhs, tile_b) bytes.
- *   d_info : device int: 0, or k > 0 when R(k,k) is exactly zero.
+ * min ||A X - B||_F for m >= n (the least-squares problem that QR solves,
+ * Sec. 2.1).  A copy of A is factorised with the trailing updates on the
+ * FP32 matrix cores (TQR_PRECISION_FP32_UPDATES; options may ask for
+ * TQR_PRECISION_FP64 instead); the norms, reflectors and T stay FP64.  Then,
+ * for each right-hand side, CGLS in FP64 on min ||(A R^{-1}) y - b||,
+ * x = R^{-1} y, from x = 0, with R the factor's triangle as a right
+ * preconditioner: every product with A and A^T uses the caller's FP64 A, and
+ * A R^{-1} is orthogonal up to the factor's rounding, so each iteration cuts
+ * the error by about cond(A) times the factor's relative accuracy, and the
+ * iteration still converges (more slowly) where that product exceeds one.
+ * The iteration of a column stops when its backward-error estimate
+ *     eta = ||R^{-T} A^T r|| / (||A||_F ||x||)          (r = b - A x)
+ * (Karlson and Walden's estimate with R in place of the triangle of
+ * [A; mu I]) is at most TQR_REFINE_ETA_TOL, when three iterations in a row
+ * have not halved ||R^{-T} A^T r|| (rounding limits it), or after
+ * `iterations`.  The residual r is recomputed as b - A x in FP64 at every
+ * iteration (the recurrence's r drifts from it by rounding).
+ * Everything runs on the stream; the stopping test is evaluated on the
+ * device.  A and B are not modified.
+ *   X       : device, n x nrhs column-major (ldx >= max(1, n)), written.
+ *   T       : device, tqr_t_elems(m, n, tile_b, 16) doubles, written.
+ *   work    : tqr_ls_mixed_workspace_bytes(m, n, nrhs, tile_b) bytes.
+ *   iterations: the most CGLS iterations per right-hand side (0..200; 0
+ *             leaves X = 0).
+ *   d_info  : device int: 0, or k > 0 when R(k,k) is exactly zero.
+ *   d_stats : device array of nrhs tqr_refine_stats, written, or NULL.
  * inner_ib is 16.  Errors: -1 m, -2 n, -3 nrhs, -4 A null, -5 lda, -6 B null,
- * -7 ldb, -8 X null, -9 ldx, -10 tile_b (64, 128 or 256), -11 iterations
- * (0..50), -12 T null, -13 work null, -14 work_bytes, -15 d_info null,
- * -16 options. */
+ * -7 ldb, -8 X null, -9 ldx, -10 tile_b (64, 128 or 256), -11 iterations,
+ * -12 T null, -13 work null, -14 work_bytes, -15 d_info null, -17 options. */
+#define TQR_REFINE_ETA_TOL 1e-15
+#define TQR_REFINE_CONVERGED 1       /* eta <= TQR_REFINE_ETA_TOL (or a zero gradient) */
+#define TQR_REFINE_STAGNATED 2       /* three iterations without halving ||R^{-T} A^T r|| */
+#define TQR_REFINE_MAX_ITERATIONS 3  /* the iteration limit was reached */
+#define TQR_REFINE_BREAKDOWN 4       /* A R^{-1} p == 0 (a singular R) */
+typedef struct tqr_refine_stats {
+    int32_t iterations;  /* CGLS iterations applied */
+    int32_t stop;        /* TQR_REFINE_* */
+    double eta;          /* the estimate at the last test, or -1 if none */
+} tqr_refine_stats;
 int64_t tqr_ls_mixed_workspace_bytes(int64_t m, int64_t n, int64_t nrhs, int tile_b);
 tqr_status tqr_solve_ls_mixed(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
                               int64_t ldb, double *X, int64_t ldx, int tile_b, int iterations, double *T, void *work,
-                              int64_t work_bytes, int32_t *d_info, hipStream_t stream, const tqr_options *options);
+                              int64_t work_bytes, int32_t *d_info, tqr_refine_stats *d_stats, hipStream_t stream,
+                              const tqr_options *options);
 
 /* ---- Batched factorisation: many independent problems in one launch ----
  * Each problem is factorised exactly as tqr_factor does it (the tiled

@@ -45,6 +45,10 @@ __global__ void k_copy_status(const SchedState *st, int32_t *out, int only_error
 }
 
 __global__ void k_set_int(int32_t *out, int32_t v) { *out = v; }
+__global__ void k_fill_u64(uint64_t *out, int64_t n, uint64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
 __global__ void k_fill_int(int32_t *out, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = v;
@@ -75,9 +79,9 @@ __global__ void k_eye(double *Q, int64_t ldq, int64_t m) {
 // split over gridDim.y blocks of columns into Part (gridDim.y x m x nrhs),
 // which k_resid_reduce adds in a fixed order.
 __global__ void k_resid_partial(const double *A, int64_t lda, int64_t m, int64_t n, const double *X, int64_t ldx,
-                                int nrhs, double *Part) {
+                                int nrhs, double *Part, const int32_t *skip) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+    if (i >= m || (skip && *skip)) return;
     const int64_t per = (n + gridDim.y - 1) / gridDim.y, j0 = blockIdx.y * per, j1 = min(n, j0 + per);
     for (int c0 = 0; c0 < nrhs; c0 += 4) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -92,77 +96,215 @@ __global__ void k_resid_partial(const double *A, int64_t lda, int64_t m, int64_t
             if (c0 + c < nrhs) Part[((int64_t)blockIdx.y * nrhs + c0 + c) * m + i] = acc[c];
     }
 }
-__global__ void k_resid_reduce(const double *Bm, int64_t ldb, const double *Rv, int64_t m, int nrhs, int chunks,
-                               const double *Part, double *F) {
+// Q = sum over the column chunks of Part (chunks x m x nrhs), in a fixed order.
+__global__ void k_sum_chunks(const double *Part, int chunks, int64_t m, int nrhs, double *Q) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= m * nrhs) return;
     const int64_t i = idx % m, c = idx / m;
     double s = 0.0;
     for (int k = 0; k < chunks; ++k) s += Part[((int64_t)k * nrhs + c) * m + i];
-    F[c * m + i] = Bm[c * ldb + i] - Rv[c * m + i] - s;
+    Q[c * m + i] = s;
 }
-// G = -A^T Rv (n x nrhs): one block per column of A, a fixed-order tree sum.
-__global__ void k_neg_atr(const double *A, int64_t lda, int64_t m, const double *Rv, int nrhs, double *G, int64_t n) {
-    __shared__ double red[NT];
+
+// Rv = B - (sum over the column chunks of Part) for the columns still
+// iterating (fixed-order sum).
+__global__ void k_resid_replace(const double *Bm, int64_t ldb, const double *Part, int chunks, int64_t m, int nrhs,
+                                double *Rv, const CglsState *st) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * nrhs) return;
+    const int64_t i = idx % m, c = idx / m;
+    if (st[c].alpha == 0.0) return;
+    double s = 0.0;
+    for (int k = 0; k < chunks; ++k) s += Part[((int64_t)k * nrhs + c) * m + i];
+    Rv[c * m + i] = Bm[c * ldb + i] - s;
+}
+
+// G = A^T Rv (n x nrhs, leading dimension n; Rv m x nrhs, leading dimension
+// m): one block per column of A, a fixed-order tree sum.
+__global__ void k_gemv_t(const double *A, int64_t lda, int64_t m, const double *Rv, int nrhs, double *G, int64_t n,
+                         const int32_t *skip) {
+    __shared__ double red[NWAVES][kNarrowRhs];
+    if (skip && *skip) return;
     const int64_t j = blockIdx.x;
-    for (int c = 0; c < nrhs; ++c) {
-        double s = 0.0;
-        for (int64_t i = threadIdx.x; i < m; i += NT) s += A[j * lda + i] * Rv[c * m + i];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = NT / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
+    const double *a = A + j * lda;
+    double s[kNarrowRhs] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < m; i += NT) {
+        const double v = a[i];
+#pragma unroll
+        for (int c = 0; c < kNarrowRhs; ++c)
+            if (c < nrhs) s[c] += v * Rv[c * m + i];
+    }
+#pragma unroll
+    for (int c = 0; c < kNarrowRhs; ++c) {
+        const double w = wave_sum(s[c]);
+        if (lane_id() == 0) red[wave_id()][c] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)nrhs) {
+        double t = 0.0;
+        for (int w = 0; w < NWAVES; ++w) t += red[w][threadIdx.x];
+        G[threadIdx.x * n + j] = t;
+    }
+}
+
+// out[j] = sum of squares of column j of A (one block per column).
+__global__ void k_col_sumsq(const double *A, int64_t lda, int64_t m, double *out) {
+    __shared__ double red[NWAVES];
+    const double *a = A + (int64_t)blockIdx.x * lda;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += NT) s += a[i] * a[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// *out = sum of v[0:n] (one block, fixed order).
+__global__ void k_sum_vec(const double *v, int64_t n, double *out) {
+    __shared__ double red[NWAVES];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += NT) s += v[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// ---- CGLS on A R^{-1} (mixed-precision least squares) ----------------------
+// One block per right-hand side c for the reductions; sums in a fixed order.
+__device__ double col_dot(const double *u, const double *v, int64_t rows) {
+    __shared__ double red[NWAVES];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < rows; i += NT) s += u[i] * v[i];
+    return block_sum(s, red);
+}
+
+// p = s, gamma = ||s||^2; every column active.
+__global__ void k_cgls_start(const double *S, int64_t n, double *P, const double *Rv, int64_t m, int nrhs,
+                             CglsState *st, int max_iter) {
+    const int c = blockIdx.x;
+    const double *sc = S + (int64_t)c * n;
+    for (int64_t i = threadIdx.x; i < n; i += NT) P[(int64_t)c * n + i] = sc[i];
+    const double g = col_dot(sc, sc, n);
+    if (threadIdx.x == 0) {
+        CglsState z{};
+        z.gamma = g;
+        z.best = g;
+        z.eta = -1.0;
+        z.active = (g > 0.0 && max_iter > 0) ? 1 : 0;
+        z.stop = g > 0.0 ? (max_iter > 0 ? 0 : TQR_REFINE_MAX_ITERATIONS) : TQR_REFINE_CONVERGED;
+        st[c] = z;
+    }
+}
+
+// alpha = gamma / ||q||^2 (q = A R^{-1} p).
+__global__ void k_cgls_step(const double *Q, int64_t m, int nrhs, CglsState *st) {
+    const int c = blockIdx.x;
+    const double *qc = Q + (int64_t)c * m;
+    const double qq = col_dot(qc, qc, m);
+    if (threadIdx.x == 0) {
+        CglsState &z = st[c];
+        if (!z.active) {
+            z.alpha = 0.0;
+        } else if (!(qq > 0.0)) {
+            z.alpha = 0.0;
+            z.active = 0;
+            z.stop = TQR_REFINE_BREAKDOWN;
+        } else {
+            z.alpha = z.gamma / qq;
+            z.iters += 1;
         }
-        if (threadIdx.x == 0) G[c * n + j] = -red[0];
-        __syncthreads();
     }
 }
-// Tiles of B (p tiles of b x wb): U = D - H on the first n rows, zero below;
-// then D's first n rows <- H (the vector [h; d2] of the augmented system).
-__global__ void k_aug_combine(double *Dt, const double *Ht, double *Ut, int b, int wb, int64_t n, int64_t total) {
+
+// x += alpha t, r -= alpha q for the active columns.
+__global__ void k_cgls_update_xr(double *Xv, const double *Tv, int64_t n, double *Rv, const double *Q, int64_t m,
+                                 int nrhs, const CglsState *st) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int64_t tile = idx / ((int64_t)b * wb), e = idx % ((int64_t)b * wb);
-    const int64_t row = tile * b + e % b;
-    if (row < n) {
-        Ut[idx] = Dt[idx] - Ht[idx];
-        Dt[idx] = Ht[idx];
-    } else {
-        Ut[idx] = 0.0;
-    }
-}
-// Y (rows x nrhs, column-major, ld rows) += the first `rows` rows of tiles Bt.
-__global__ void k_tiles_add_to_cm(const double *Bt, int b, int wb, double *Y, int64_t rows, int nrhs) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t rows = m > n ? m : n;
     if (idx >= rows * nrhs) return;
-    const int64_t r = idx % rows, c = idx / rows;
-    Y[c * rows + r] += Bt[(r / b) * b * wb + c * b + r % b];
+    const int64_t i = idx % rows, c = idx / rows;
+    const double a = st[c].alpha;
+    if (a == 0.0) return;
+    if (i < n) Xv[c * n + i] += a * Tv[c * n + i];
+    if (i < m) Rv[c * m + i] -= a * Q[c * m + i];
 }
+
+// beta = ||s||^2 / gamma and the stopping test on
+// eta = ||s|| / (||A||_F ||x||) (s = R^{-T} A^T r, the backward-error
+// estimate of Karlson and Walden with R for the triangle of [A; mu I],
+// exact when mu = ||r|| / ||x|| is below A's smallest singular value):
+// converged when eta <= TQR_REFINE_ETA_TOL; stagnated when three iterations
+// in a row have not halved the smallest ||s|| seen (rounding then decides s).
+__global__ void k_cgls_next(const double *S, const double *Xv, const double *Rv, int64_t n, int64_t m, int nrhs,
+                            const double *fro2, CglsState *st, int iter) {
+    const int c = blockIdx.x;
+    const double *sc = S + (int64_t)c * n;
+    const double ss = col_dot(sc, sc, n);
+    const double xx = col_dot(Xv + (int64_t)c * n, Xv + (int64_t)c * n, n);
+    if (threadIdx.x == 0) {
+        CglsState &z = st[c];
+        if (!z.active) {
+            z.beta = 0.0;
+            return;
+        }
+        const double den = sqrt(*fro2) * sqrt(xx);
+        z.eta = den > 0.0 ? sqrt(ss) / den : -1.0;
+        z.beta = z.gamma > 0.0 ? ss / z.gamma : 0.0;
+        z.gamma = ss;
+        // progress: ||s|| at least halved since the best value so far
+        if (ss < 0.25 * z.best) {
+            z.best = ss;
+            z.since = 0;
+        } else {
+            z.since += 1;
+        }
+        if (!(ss > 0.0) || (z.eta >= 0.0 && z.eta <= TQR_REFINE_ETA_TOL)) {
+            z.active = 0;
+            z.stop = TQR_REFINE_CONVERGED;
+        } else if (z.since >= 3) {
+            z.active = 0;
+            z.stop = TQR_REFINE_STAGNATED;
+        }
+    }
+}
+
+// p = s + beta p for the active columns.
+__global__ void k_cgls_update_p(double *P, const double *S, int64_t n, int nrhs, const CglsState *st) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nrhs) return;
+    const int64_t c = idx / n;
+    if (!st[c].active) return;
+    P[idx] = S[idx] + st[c].beta * P[idx];
+}
+
+// *done = 1 when no column of the chunk is still iterating.
+__global__ void k_cgls_alldone(const CglsState *st, int nrhs, int32_t *done) {
+    if (threadIdx.x != 0) return;
+    int any = 0;
+    for (int c = 0; c < nrhs; ++c) any |= st[c].active;
+    *done = any ? 0 : 1;
+}
+
+// Statistics of an empty problem (nothing to refine).
+__global__ void k_refine_stats_empty(tqr_refine_stats *out, int64_t nrhs) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nrhs) out[c] = tqr_refine_stats{0, TQR_REFINE_CONVERGED, 0.0};
+}
+
+// Per-column statistics for the caller; a column still active ran out of
+// iterations.
+__global__ void k_cgls_report(const CglsState *st, int nrhs, tqr_refine_stats *out) {
+    const int c = threadIdx.x;
+    if (c >= nrhs) return;
+    tqr_refine_stats r;
+    r.iterations = st[c].iters;
+    r.stop = st[c].active ? TQR_REFINE_MAX_ITERATIONS : st[c].stop;
+    r.eta = st[c].eta;
+    out[c] = r;
+}
+
 __global__ void k_copy_cm(const double *S, int64_t lds, double *D, int64_t ldd, int64_t rows, int nrhs, double scale) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= rows * nrhs) return;
     const int64_t r = idx % rows, c = idx / rows;
     D[c * ldd + r] = S ? scale * S[c * lds + r] : 0.0;
-}
-
-// Column-major blocks of the augmented-system refinement: U = F[0:n] - G and
-// F[0:n] <- G (the vector [h; d2]); rows n.. of F are kept.
-__global__ void k_aug_combine_cm(double *F, int64_t ldf, const double *G, int64_t ldg, double *U, int64_t ldu,
-                                 int64_t n, int nrhs) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * nrhs) return;
-    const int64_t r = idx % n, c = idx / n;
-    const double g = G[c * ldg + r];
-    U[c * ldu + r] = F[c * ldf + r] - g;
-    F[c * ldf + r] = g;
-}
-// D += S (rows x nrhs, column-major).
-__global__ void k_add_cm(const double *S, int64_t lds, double *D, int64_t ldd, int64_t rows, int nrhs) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * nrhs) return;
-    const int64_t r = idx % rows, c = idx / rows;
-    D[c * ldd + r] += S[c * lds + r];
 }
 
 __global__ void k_diag_info(const double *W, int p, int b, int64_t n, int32_t *info) {
@@ -217,15 +359,6 @@ std::vector<int64_t> serial_order(const TrsmGraph &g) {
     // G(i,j) needs D(j): rows are solved bottom-up, so D(j) precedes every G(i,j)
     return out;
 }
-std::vector<int64_t> serial_order(const TrsmTGraph &g) {
-    std::vector<int64_t> out;
-    for (int64_t i = 0; i < g.q; ++i) {
-        for (int64_t j = 0; j < i; ++j) out.push_back(g.encode_g(i, j));
-        out.push_back(g.encode_d(i));
-    }
-    return out;
-}
-
 template <class F>
 tqr_status dispatch(int b, int ib, F &&f) {
 #define TQR_CASE(BB, II) \
@@ -413,7 +546,8 @@ int64_t tqr_ls_mixed_workspace_bytes(int64_t m, int64_t n, int64_t nrhs, int til
 
 tqr_status tqr_solve_ls_mixed(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
                               int64_t ldb, double *X, int64_t ldx, int tile_b, int iterations, double *T, void *work,
-                              int64_t work_bytes, int32_t *d_info, hipStream_t stream, const tqr_options *options) {
+                              int64_t work_bytes, int32_t *d_info, tqr_refine_stats *d_stats, hipStream_t stream,
+                              const tqr_options *options) {
     g_err.clear();
     if (m < 0 || m < n) return set_err(-1, "m must be >= max(n, 0)");
     if (n < 0) return set_err(-2, "n must be >= 0");
@@ -425,19 +559,22 @@ tqr_status tqr_solve_ls_mixed(int64_t m, int64_t n, int64_t nrhs, const double *
     if (!X) return set_err(-8, "X is null");
     if (ldx < std::max<int64_t>(1, n)) return set_err(-9, "ldx < max(1, n)");
     if (!(tile_b == 64 || tile_b == 128 || tile_b == 256)) return set_err(-10, "tile_b must be 64, 128 or 256");
-    if (iterations < 0 || iterations > 50) return set_err(-11, "iterations must be in 0..50");
+    if (iterations < 0 || iterations > 200) return set_err(-11, "iterations must be in 0..200");
     if (!T) return set_err(-12, "T is null");
     if (!work) return set_err(-13, "work is null");
     const MixedSizes ms = mixed_sizes(std::max<int64_t>(m, 1), std::max<int64_t>(n, 1), nrhs, tile_b);
     if (work_bytes < ms.total) return set_err(-14, "work_bytes too small");
     if (!d_info) return set_err(-15, "d_info is null");
     if (check_opts(options) != TQR_OK || (options && options->mode != TQR_MODE_PERSISTENT))
-        return set_err(-16, "bad options (struct_size, precision, or a mode other than TQR_MODE_PERSISTENT)");
+        return set_err(-17, "bad options (struct_size, precision, or a mode other than TQR_MODE_PERSISTENT)");
     if (m == 0 || n == 0) {
         hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_info, 0);
         if (n > 0)
             hipLaunchKernelGGL(k_copy_cm, dim3((unsigned)cdiv(n * nrhs, 256)), dim3(256), 0, stream, nullptr, 0, X, ldx,
                                n, (int)nrhs, 0.0);
+        if (d_stats)
+            hipLaunchKernelGGL(k_refine_stats_empty, dim3((unsigned)cdiv(nrhs, 256)), dim3(256), 0, stream, d_stats,
+                               nrhs);
         HIPCHK(hipGetLastError());
         return TQR_OK;
     }
@@ -452,7 +589,7 @@ tqr_status tqr_solve_ls_mixed(int64_t m, int64_t n, int64_t nrhs, const double *
     o.event_begin = o.event_end = nullptr;
     if (options && options->event_begin) HIPCHK(hipEventRecord((hipEvent_t)options->event_begin, stream));
     tqr_status st = dispatch(tile_b, 16, [&](const PairFns &f) {
-        return f.mixed(m, n, nrhs, A, lda, B, ldb, X, ldx, iterations, T, work, d_info, stream, o);
+        return f.mixed(m, n, nrhs, A, lda, B, ldb, X, ldx, iterations, T, work, d_info, d_stats, stream, o);
     });
     if (st != TQR_OK) return st;
     if (options && options->event_end) HIPCHK(hipEventRecord((hipEvent_t)options->event_end, stream));

@@ -307,44 +307,4 @@ struct TrsmGraph {
     }
 };
 
-// Forward substitution with the transposed tiled R (R^T Y = G, the lower
-// triangular solve of least-squares refinement): G'(i,j), j < i:
-// Y_i -= R_ji^T X_j;  D'(i): X_i = R_ii^{-T} Y_i.  Row i holds G'(i,0), ...,
-// G'(i,i-1), D'(i).  G'(i,j) <- D'(j), G'(i,j-1);  D'(i) <- G'(i,i-1).
-struct TrsmTGraph {
-    int64_t q;
-    TQR_HD explicit TrsmTGraph(int64_t q_) : q(q_) {}
-    TQR_HD int64_t offset(int64_t i) const { return i * (i + 1) / 2; }
-    TQR_HD int64_t num_tasks() const { return offset(q); }
-    TQR_HD int64_t encode_g(int64_t i, int64_t j) const { return offset(i) + j; }
-    TQR_HD int64_t encode_d(int64_t i) const { return offset(i) + i; }
-    // kind 0 = D' (diagonal solve), 1 = G' (update)
-    TQR_HD Task decode(int64_t t) const {
-        int64_t lo = 0, hi = q - 1;
-        while (lo < hi) {
-            int64_t mid = (lo + hi + 1) / 2;
-            if (offset(mid) <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        Task r;
-        r.i = (int)lo;
-        r.j = (int)(t - offset(lo));
-        r.k = 0;
-        r.c = 0;
-        r.kind = (r.j == r.i) ? 0 : 1;
-        return r;
-    }
-    TQR_HD int indegree(const Task &t) const {
-        if (t.kind == 0) return t.i > 0 ? 1 : 0;
-        return 1 + (t.j > 0 ? 1 : 0);
-    }
-    TQR_HD int num_successors(const Task &t) const { return t.kind == 0 ? (int)(q - 1 - t.i) : 1; }
-    TQR_HD int64_t successor(const Task &t, int n) const {
-        if (t.kind == 0) return encode_g(t.i + 1 + n, t.i);  // G'(i', i) for i' > i
-        return (t.j + 1 < t.i) ? encode_g(t.i, t.j + 1) : encode_d(t.i);
-    }
-};
-
 }  // namespace tqr

@@ -1359,78 +1359,6 @@ struct TrsmBody {
     }
 };
 
-// Forward substitution with R^T on the tiles of B (refinement of least
-// squares): G'(i,j): Y_i -= R_ji^T X_j;  D'(i): solve R_ii^T X_i = Y_i.
-template <int B>
-struct TrsmTBody {
-    const double *W;
-    double *Bt;
-    int p, wb;
-    int64_t nrow;
-    __device__ const double *tile(int i, int j) const { return W + ((int64_t)j * p + i) * B * B; }
-    __device__ double *btile(int i) const { return Bt + (int64_t)i * B * wb; }
-    __device__ __forceinline__ void run(const Task &t, double *smem) const {
-        if (t.kind == 1) {
-            // A operand of k-slice (kb, s): R_ji^T[16rb + perm(l%16)][16kb + 4s + l/16]
-            //   = R_ji[16kb + 4s + l/16][16rb + perm(l%16)], perm = strip_row_perm
-            const double *R = tile(t.j, t.i);
-            const double *X = btile(t.j);
-            double *Y = btile(t.i);
-            const int l = lane_id();
-            for (int col0 = 16 * wave_id(); col0 < wb; col0 += 16 * NWAVES) {
-                Strip<B> C;
-                strip_load<B>(C, Y + (size_t)col0 * B, B);
-                const double *xp = X + (size_t)(col0 + (l & 15)) * B + (l >> 4);
-                const double *rp = R + (size_t)strip_row_perm(l & 15) * B + (l >> 4);
-#pragma unroll 1
-                for (int kb = 0; kb < B / 16; ++kb) {
-                    const d4 x = -ld4s(xp + 16 * kb, 4);
-                    const double *rk = rp + 16 * kb;
-#pragma unroll
-                    for (int rb = 0; rb < B / 16; ++rb) {
-                        const double *q = rk + (size_t)16 * rb * B;
-                        C.v[rb] = mfma(q[0], x.x, C.v[rb]);
-                        C.v[rb] = mfma(q[4], x.y, C.v[rb]);
-                        C.v[rb] = mfma(q[8], x.z, C.v[rb]);
-                        C.v[rb] = mfma(q[12], x.w, C.v[rb]);
-                    }
-                }
-                strip_store<B>(C, Y + (size_t)col0 * B, B);
-            }
-            return;
-        }
-        // D'(i): R_ii^T X_i = Y_i, forward over the rows that are not padding
-        const double *R = tile(t.i, t.i);
-        double *Y = btile(t.i);
-        const int64_t rem = nrow - (int64_t)t.i * B;
-        const int nloc = (int)(rem < B ? rem : B);
-        const int tid = threadIdx.x;
-        double *y = smem;  // B x 16
-        for (int g0 = 0; g0 < wb; g0 += 16) {
-            for (int idx = tid; idx < B * 16; idx += NT) {
-                const int r = idx % B, c = idx / B;
-                y[idx] = (r < nloc) ? Y[(size_t)(g0 + c) * B + r] : 0.0;
-            }
-            __syncthreads();
-            for (int cidx = 0; cidx < nloc; ++cidx) {
-                if (tid < 16) y[cidx + tid * B] = y[cidx + tid * B] / R[(size_t)cidx * B + cidx];
-                __syncthreads();
-                const int rest = nloc - cidx - 1;
-                for (int idx = tid; idx < rest * 16; idx += NT) {
-                    const int r = cidx + 1 + idx % rest, c = idx / rest;
-                    y[r + c * B] -= R[(size_t)r * B + cidx] * y[cidx + c * B];
-                }
-                __syncthreads();
-            }
-            for (int idx = tid; idx < B * 16; idx += NT) {
-                const int r = idx % B, c = idx / B;
-                Y[(size_t)(g0 + c) * B + r] = y[idx];
-            }
-            __syncthreads();
-        }
-    }
-};
-
 // ===========================================================================
 // The persistent scheduler: every workgroup repeatedly takes the
 // highest-priority ready task, runs it, and releases its successors; a
@@ -1613,21 +1541,45 @@ __global__ void __launch_bounds__(NT) k_one_task(G g, Body body, int64_t t) {
 __global__ void k_copy_status(const SchedState *st, int32_t *out, int only_errors);
 __global__ void k_set_int(int32_t *out, int32_t v);
 __global__ void k_fill_int(int32_t *out, int64_t n, int32_t v);
+__global__ void k_fill_u64(uint64_t *out, int64_t n, uint64_t v);
 __global__ void k_unit_lower(const double *__restrict__ W, int p, int b, double *__restrict__ Vd);
 __global__ void k_eye(double *Q, int64_t ldq, int64_t m);
 constexpr int kResidChunks = 16;
 __global__ void k_resid_partial(const double *A, int64_t lda, int64_t m, int64_t n, const double *X, int64_t ldx,
-                                int nrhs, double *Part);
-__global__ void k_resid_reduce(const double *Bm, int64_t ldb, const double *Rv, int64_t m, int nrhs, int chunks,
-                               const double *Part, double *F);
-__global__ void k_neg_atr(const double *A, int64_t lda, int64_t m, const double *Rv, int nrhs, double *G, int64_t n);
-__global__ void k_aug_combine(double *Dt, const double *Ht, double *Ut, int b, int wb, int64_t n, int64_t total);
-__global__ void k_tiles_add_to_cm(const double *Bt, int b, int wb, double *Y, int64_t rows, int nrhs);
+                                int nrhs, double *Part, const int32_t *skip);
+__global__ void k_sum_chunks(const double *Part, int chunks, int64_t m, int nrhs, double *Q);
+struct CglsState;
+__global__ void k_resid_replace(const double *Bm, int64_t ldb, const double *Part, int chunks, int64_t m, int nrhs,
+                                double *Rv, const CglsState *st);
+__global__ void k_gemv_t(const double *A, int64_t lda, int64_t m, const double *Rv, int nrhs, double *G, int64_t n,
+                         const int32_t *skip);
+__global__ void k_col_sumsq(const double *A, int64_t lda, int64_t m, double *out);
+__global__ void k_sum_vec(const double *v, int64_t n, double *out);
+// CGLS state of one right-hand side (device)
+struct CglsState {
+    double gamma;     // ||s||^2 of the current s = R^{-T} A^T r
+    double alpha;     // step of the current iteration
+    double beta;      // p = s + beta p
+    double eta;       // ||R^{-T} A^T r|| / (||A||_F ||x||) at the last test
+    double best;      // smallest ||s||^2 seen
+    int32_t active;   // 0 once the column has stopped
+    int32_t iters;    // iterations applied
+    int32_t stop;     // TQR_REFINE_* reason
+    int32_t since;    // tests since the smallest ||s||^2 was last halved
+};
+__global__ void k_cgls_start(const double *S, int64_t n, double *P, const double *Rv, int64_t m, int nrhs,
+                             CglsState *st, int max_iter);
+__global__ void k_cgls_step(const double *Q, int64_t m, int nrhs, CglsState *st);
+__global__ void k_cgls_update_xr(double *Xv, const double *Tv, int64_t n, double *Rv, const double *Q, int64_t m,
+                                 int nrhs, const CglsState *st);
+__global__ void k_cgls_next(const double *S, const double *Xv, const double *Rv, int64_t n, int64_t m, int nrhs,
+                            const double *fro2, CglsState *st, int iter);
+__global__ void k_cgls_update_p(double *P, const double *S, int64_t n, int nrhs, const CglsState *st);
+__global__ void k_cgls_report(const CglsState *st, int nrhs, tqr_refine_stats *out);
+__global__ void k_cgls_alldone(const CglsState *st, int nrhs, int32_t *done);
+__global__ void k_refine_stats_empty(tqr_refine_stats *out, int64_t nrhs);
 __global__ void k_copy_cm(const double *S, int64_t lds, double *D, int64_t ldd, int64_t rows, int nrhs, double scale);
 __global__ void k_diag_info(const double *W, int p, int b, int64_t n, int32_t *info);
-__global__ void k_aug_combine_cm(double *F, int64_t ldf, const double *G, int64_t ldg, double *U, int64_t ldu,
-                                 int64_t n, int nrhs);
-__global__ void k_add_cm(const double *S, int64_t lds, double *D, int64_t ldd, int64_t rows, int nrhs);
 
 // ===========================================================================
 // Host side
@@ -1664,9 +1616,10 @@ inline bool narrow_ok(int b, int ib, int64_t nrhs) { return ib == 16 && b >= 64 
 // Workspace: [tiles p*q*b*b][dense diagonal V q*b*b][B tiles p*b*wb][scheduler]
 // [R_kk chain progress words p*q int32][narrow-rhs words and hand-over blocks]
 // The narrow region (only when narrow_ok): 64 control ints (apply: ticket,
-// abort at 0, 1; triangular solves: at 2, 3), the apply flags (q*p*b/16),
-// the solve flags (one per 64-row block), then the apply hand-over blocks
-// (q*p*b*kNarrowRhs doubles) and the published solution blocks.
+// abort at 0, 1; triangular solves: at 2, 3; the refinement's "all columns
+// stopped" word at 4), then the apply hand-over blocks (q*p*b*kNarrowRhs
+// doubles) and the published solution blocks (one 64 x kNarrowRhs block per
+// 64 rows of R).
 struct Sizes {
     int64_t p, q, tiles_bytes, vd_bytes, btiles_bytes, sched_bytes, prog_bytes, total;
     int64_t nar_ints, nar_h_bytes, nar_x_bytes, nar_bytes;
@@ -1685,14 +1638,13 @@ inline Sizes sizes_of(int64_t m, int64_t n, int64_t nrhs, int b) {
     if (nrhs > 0) {
         nt = std::max(nt, ApplyGraph(z.p, z.q, cdiv(wb_of(nrhs), kStripCols), true).num_tasks());
         nt = std::max(nt, TrsmGraph(z.q).num_tasks());
-        nt = std::max(nt, TrsmTGraph(z.q).num_tasks());
     }
     z.sched_bytes = align256(sched_bytes(nt));
     z.prog_bytes = align256(4 * z.p * z.q * 4);
     z.nar_ints = z.nar_h_bytes = z.nar_x_bytes = z.nar_bytes = 0;
     if (nrhs >= 1 && nrhs <= kNarrowRhs && b >= 64) {
         const int64_t nb = cdiv(std::max<int64_t>(n, 1), kTrsvRows);
-        z.nar_ints = 64 + z.q * z.p * (b / 16) + nb;
+        z.nar_ints = 64;
         z.nar_h_bytes = align256(z.q * z.p * (int64_t)b * kNarrowRhs * 8);
         z.nar_x_bytes = align256(nb * kTrsvRows * kNarrowRhs * 8);
         z.nar_bytes = align256(z.nar_ints * 4) + z.nar_h_bytes + z.nar_x_bytes;
@@ -1703,15 +1655,15 @@ inline Sizes sizes_of(int64_t m, int64_t n, int64_t nrhs, int b) {
 
 // Pointers into the narrow region of a workspace laid out by sizes_of.
 struct NarrowMem {
-    int32_t *ints, *apply_flags, *trsv_flags;
+    int32_t *ints;
     double *H, *X;
+    const int32_t *skip = nullptr;  // the triangular solves return at once while *skip != 0
 };
 inline NarrowMem narrow_mem(void *work, const Sizes &z, int b) {
+    (void)b;
     char *base = reinterpret_cast<char *>(work) + z.narrow_offset();
     NarrowMem nm;
     nm.ints = reinterpret_cast<int32_t *>(base);
-    nm.apply_flags = nm.ints + 64;
-    nm.trsv_flags = nm.apply_flags + z.q * z.p * (b / 16);
     nm.H = reinterpret_cast<double *>(base + align256(z.nar_ints * 4));
     nm.X = reinterpret_cast<double *>(base + align256(z.nar_ints * 4) + z.nar_h_bytes);
     return nm;
@@ -1744,7 +1696,6 @@ inline int cu_count() {
 std::vector<int64_t> serial_order(const FactorGraph &g);
 std::vector<int64_t> serial_order(const ApplyGraph &g);
 std::vector<int64_t> serial_order(const TrsmGraph &g);
-std::vector<int64_t> serial_order(const TrsmTGraph &g);
 template <class G>
 int64_t trace_count(const G &g) { return g.num_tasks(); }
 template <>
@@ -1892,15 +1843,6 @@ tqr_status trsm_impl(int64_t m, int64_t n, int64_t nrhs, const double *W, double
                      opt ? opt->status : nullptr, 1);
 }
 
-template <int B>
-tqr_status trsmt_impl(int64_t m, int64_t n, int64_t nrhs, const double *W, double *Bt, void *sched, hipStream_t stream,
-                      const tqr_options *opt = nullptr) {
-    const int64_t p = cdiv(m, B), q = cdiv(n, B), wb = wb_of(nrhs);
-    TrsmTGraph g(q);
-    return run_graph(g, TrsmTBody<B>{W, Bt, (int)p, (int)wb, n}, sched, (size_t)B * 16 * 8, opt, stream,
-                     opt ? opt->status : nullptr, 1);
-}
-
 // ---- narrow right-hand sides (tqr_narrow.h) --------------------------------
 // Q^T B (trans) or Q B in place on the column-major m x nrhs block Bm
 // (1 <= nrhs <= kNarrowRhs), one workgroup per row tile.  Control words and
@@ -1913,9 +1855,11 @@ tqr_status narrow_apply(bool trans, int64_t m, int64_t n, int64_t nrhs, const do
         return set_err(TQR_EDEVICE, "narrow application needs inner_ib 16 and tile_b >= 64");
     } else {
         const int64_t p = cdiv(m, B), q = cdiv(n, B);
-        const int64_t nflags = q * p * (B / 16);
-        hipLaunchKernelGGL(k_fill_int, dim3((unsigned)cdiv(64 + nflags, 256)), dim3(256), 0, stream, nm.ints,
-                           64 + nflags, 0);
+        const int nr = nrhs == 1 ? 1 : (nrhs == 2 ? 2 : 4);
+        const int64_t nh = q * p * B * nr;
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, stream, nm.ints, (int64_t)2, 0);
+        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)cdiv(nh, 256)), dim3(256), 0, stream,
+                           reinterpret_cast<uint64_t *>(nm.H), nh, kPendingBits);
         NarrowApplyArgs a;
         a.W = W;
         a.Vd = Vd;
@@ -1927,7 +1871,6 @@ tqr_status narrow_apply(bool trans, int64_t m, int64_t n, int64_t nrhs, const do
         a.p = (int)p;
         a.q = (int)q;
         a.H = nm.H;
-        a.flags = nm.apply_flags;
         a.ctl.ticket = nm.ints;
         a.ctl.abort = nm.ints + 1;
         a.ctl.status = opt ? opt->status : nullptr;
@@ -1955,8 +1898,11 @@ tqr_status narrow_trsv(bool trans, int64_t m, int64_t n, int64_t nrhs, const dou
                        const NarrowMem &nm, hipStream_t stream, const tqr_options *opt) {
     const int64_t p = cdiv(m, B);
     const int64_t nb = cdiv(n, kTrsvRows);
+    const int nr = nrhs == 1 ? 1 : (nrhs == 2 ? 2 : 4);
+    const int64_t nx = nb * kTrsvRows * nr;
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, stream, nm.ints + 2, (int64_t)2, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)cdiv(nb, 256)), dim3(256), 0, stream, nm.trsv_flags, nb, 0);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)cdiv(nx, 256)), dim3(256), 0, stream,
+                       reinterpret_cast<uint64_t *>(nm.X), nx, kPendingBits);
     NarrowTrsvArgs a;
     a.W = W;
     a.p = (int)p;
@@ -1965,7 +1911,7 @@ tqr_status narrow_trsv(bool trans, int64_t m, int64_t n, int64_t nrhs, const dou
     a.ldy = ldy;
     a.nrhs = (int)nrhs;
     a.X = nm.X;
-    a.flags = nm.trsv_flags;
+    a.skip = nm.skip;
     a.ctl.ticket = nm.ints + 2;
     a.ctl.abort = nm.ints + 3;
     a.ctl.status = opt ? opt->status : nullptr;
@@ -2037,47 +1983,55 @@ tqr_status solve_impl(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda
 }
 
 // Workspace of the mixed solver: the solve layout (tiles, dense V, B tiles,
-// scheduler, progress words), two more B-tile buffers, x, r, f, g and the
-// partial sums of A x.
+// scheduler, progress words, narrow region), then the refinement's vectors
+// for one chunk of at most kNarrowRhs right-hand sides: x, p, t, s (n rows),
+// r, q (m rows), the partial sums of A t, the per-column state and ||A||_F^2.
 struct MixedSizes {
     Sizes z;
-    int64_t ht, ut, xv, rv, f, g, part, total;
+    int64_t x, p, t, s, r, q, part, colsq, state, total;
 };
 inline MixedSizes mixed_sizes(int64_t m, int64_t n, int64_t nrhs, int b) {
     MixedSizes s;
-    s.z = sizes_of(m, n, nrhs, b);
-    const int64_t bt = s.z.btiles_bytes;
-    s.ht = s.z.total;
-    s.ut = s.ht + bt;
-    s.xv = s.ut + bt;
-    s.rv = s.xv + align256(n * nrhs * 8);
-    s.f = s.rv + align256(m * nrhs * 8);
-    s.g = s.f + align256(m * nrhs * 8);
-    s.part = s.g + align256(n * nrhs * 8);
-    s.total = s.part + align256((int64_t)kResidChunks * m * nrhs * 8);
+    s.z = sizes_of(m, n, std::min<int64_t>(nrhs, kNarrowRhs), b);
+    const int64_t nv = align256(n * kNarrowRhs * 8), mv = align256(m * kNarrowRhs * 8);
+    s.x = s.z.total;
+    s.p = s.x + nv;
+    s.t = s.p + nv;
+    s.s = s.t + nv;
+    s.r = s.s + nv;
+    s.q = s.r + mv;
+    s.part = s.q + mv;
+    s.colsq = s.part + align256((int64_t)kResidChunks * m * kNarrowRhs * 8);
+    s.state = s.colsq + align256(n * 8);
+    s.total = s.state + align256((int64_t)kNarrowRhs * (int64_t)sizeof(CglsState) + 64);
     return s;
 }
 
 // Mixed-precision least squares (tqr_solve_ls_mixed after its argument
-// checks; inner block 16): the factorisation in the requested precision, then
-// `iterations` steps of FP64 refinement of the augmented system.
+// checks; inner block 16): the factorisation in the requested precision,
+// then, for each chunk of at most kNarrowRhs right-hand sides, CGLS in FP64
+// on min ||(A R^{-1}) y - b||, x = R^{-1} y, from x = 0 (R, the factor's
+// triangle, as a right preconditioner: A R^{-1} is orthogonal up to the
+// factor's rounding, so few iterations reach FP64 accuracy).  Every product
+// with A and A^T is taken with the caller's FP64 A; the triangular solves use
+// the narrow pipelines; the step lengths and the stopping test are computed
+// on the device (no host synchronisation).
 template <int B>
 tqr_status mixed_impl(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *Bm, int64_t ldb,
                       double *X, int64_t ldx, int iterations, double *T, void *work, int32_t *d_info,
-                      hipStream_t stream, const tqr_options &o) {
+                      tqr_refine_stats *stats, hipStream_t stream, const tqr_options &o) {
     const MixedSizes ms = mixed_sizes(std::max<int64_t>(m, 1), std::max<int64_t>(n, 1), nrhs, B);
     const Sizes &z = ms.z;
     char *wbase = reinterpret_cast<char *>(work);
     double *W = reinterpret_cast<double *>(wbase);
     double *Vd = reinterpret_cast<double *>(wbase + z.tiles_bytes);
-    double *Bt = reinterpret_cast<double *>(wbase + z.tiles_bytes + z.vd_bytes);
     void *sched = wbase + z.tiles_bytes + z.vd_bytes + z.btiles_bytes;
-    double *Ht = reinterpret_cast<double *>(wbase + ms.ht), *Ut = reinterpret_cast<double *>(wbase + ms.ut);
-    double *Xv = reinterpret_cast<double *>(wbase + ms.xv), *Rv = reinterpret_cast<double *>(wbase + ms.rv);
-    double *F = reinterpret_cast<double *>(wbase + ms.f), *G = reinterpret_cast<double *>(wbase + ms.g);
-    double *Part = reinterpret_cast<double *>(wbase + ms.part);
-    const int64_t wb = wb_of(nrhs), btot = z.p * B * wb;
-    const unsigned gm = (unsigned)cdiv(m * nrhs, 256), gn = (unsigned)cdiv(n * nrhs, 256);
+    double *xv = reinterpret_cast<double *>(wbase + ms.x), *pv = reinterpret_cast<double *>(wbase + ms.p);
+    double *tv = reinterpret_cast<double *>(wbase + ms.t), *sv = reinterpret_cast<double *>(wbase + ms.s);
+    double *rv = reinterpret_cast<double *>(wbase + ms.r), *qv = reinterpret_cast<double *>(wbase + ms.q);
+    double *part = reinterpret_cast<double *>(wbase + ms.part), *colsq = reinterpret_cast<double *>(wbase + ms.colsq);
+    CglsState *st = reinterpret_cast<CglsState *>(wbase + ms.state);
+    double *fro2 = reinterpret_cast<double *>(wbase + ms.state + kNarrowRhs * sizeof(CglsState));
     hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, (unsigned)z.q), dim3(256), 0, stream, A, lda, m, n, W,
                        (int)z.p, B, B);
     FactorGraph g(z.p, z.q, B);
@@ -2093,60 +2047,58 @@ tqr_status mixed_impl(int64_t m, int64_t n, int64_t nrhs, const double *A, int64
     }
     if (s1 != TQR_OK) return s1;
     hipLaunchKernelGGL(k_diag_info, dim3(1), dim3(256), 0, stream, W, (int)z.p, B, n, d_info);
-    hipLaunchKernelGGL(k_copy_cm, dim3(gn), dim3(256), 0, stream, nullptr, 0, Xv, n, n, (int)nrhs, 0.0);
-    hipLaunchKernelGGL(k_copy_cm, dim3(gm), dim3(256), 0, stream, Bm, ldb, Rv, m, m, (int)nrhs, 1.0);
-    if (narrow_ok(B, 16, nrhs)) {
-        // the same refinement with the narrow kernels: F, G and U (= Ut as an
-        // n x nrhs column-major block) are worked on in place
-        const NarrowMem nm = narrow_mem(work, z, B);
+    // ||A||_F^2 (columns, then a fixed-order sum)
+    hipLaunchKernelGGL(k_col_sumsq, dim3((unsigned)n), dim3(NT), 0, stream, A, lda, m, colsq);
+    hipLaunchKernelGGL(k_sum_vec, dim3(1), dim3(NT), 0, stream, colsq, n, fro2);
+    NarrowMem nm = narrow_mem(work, z, B);
+    int32_t *done = nm.ints + 4;  // every column of the chunk has stopped
+    const unsigned gn4 = (unsigned)cdiv(n * kNarrowRhs, 256), gm4 = (unsigned)cdiv(m * kNarrowRhs, 256);
+    for (int64_t c0 = 0; c0 < nrhs; c0 += kNarrowRhs) {
+        const int nc = (int)std::min<int64_t>(kNarrowRhs, nrhs - c0);
+        // x = 0, r = b, s = R^{-T} A^T b, p = s, gamma = ||s||^2
+        hipLaunchKernelGGL(k_copy_cm, dim3(gn4), dim3(256), 0, stream, nullptr, 0, xv, n, n, nc, 0.0);
+        hipLaunchKernelGGL(k_copy_cm, dim3(gm4), dim3(256), 0, stream, Bm + c0 * ldb, ldb, rv, m, m, nc, 1.0);
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, stream, done, (int64_t)1, 0);
+        nm.skip = nullptr;
+        hipLaunchKernelGGL(k_gemv_t, dim3((unsigned)n), dim3(NT), 0, stream, A, lda, m, rv, nc, sv, n, nullptr);
+        s1 = narrow_trsv<B>(true, m, n, nc, W, sv, n, nm, stream, &o);
+        if (s1 != TQR_OK) return s1;
+        hipLaunchKernelGGL(k_cgls_start, dim3(nc), dim3(NT), 0, stream, sv, n, pv, rv, m, nc, st, iterations);
+        hipLaunchKernelGGL(k_cgls_alldone, dim3(1), dim3(64), 0, stream, st, nc, done);
+        // once every column has stopped, the remaining iterations' products
+        // and solves return at once (no host synchronisation to cut the loop)
+        nm.skip = done;
         for (int it = 0; it < iterations; ++it) {
+            // t = R^{-1} p, q = A t, alpha = gamma / ||q||^2, x += alpha t, r -= alpha q
+            hipLaunchKernelGGL(k_copy_cm, dim3(gn4), dim3(256), 0, stream, pv, n, tv, n, n, nc, 1.0);
+            s1 = narrow_trsv<B>(false, m, n, nc, W, tv, n, nm, stream, &o);
+            if (s1 != TQR_OK) return s1;
             hipLaunchKernelGGL(k_resid_partial, dim3((unsigned)cdiv(m, 256), kResidChunks), dim3(256), 0, stream, A,
-                               lda, m, n, Xv, n, (int)nrhs, Part);
-            hipLaunchKernelGGL(k_resid_reduce, dim3(gm), dim3(256), 0, stream, Bm, ldb, Rv, m, (int)nrhs, kResidChunks,
-                               Part, F);
-            hipLaunchKernelGGL(k_neg_atr, dim3((unsigned)n), dim3(NT), 0, stream, A, lda, m, Rv, (int)nrhs, G, n);
-            s1 = narrow_apply<B, 16>(true, m, n, nrhs, T, W, Vd, F, m, nm, stream, &o);  // d = Q^T f
+                               lda, m, n, tv, n, nc, part, done);
+            hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)cdiv(m * nc, 256)), dim3(256), 0, stream, part,
+                               kResidChunks, m, nc, qv);
+            hipLaunchKernelGGL(k_cgls_step, dim3(nc), dim3(NT), 0, stream, qv, m, nc, st);
+            hipLaunchKernelGGL(k_cgls_update_xr, dim3((unsigned)cdiv(std::max(m, n) * nc, 256)), dim3(256), 0, stream,
+                               xv, tv, n, rv, qv, m, nc, st);
+            // residual replacement: r = b - A x in FP64 (the recurrence's r
+            // drifts from the true residual by rounding, and the stopping
+            // test must see the true one)
+            hipLaunchKernelGGL(k_resid_partial, dim3((unsigned)cdiv(m, 256), kResidChunks), dim3(256), 0, stream, A,
+                               lda, m, n, xv, n, nc, part, done);
+            hipLaunchKernelGGL(k_resid_replace, dim3((unsigned)cdiv(m * nc, 256)), dim3(256), 0, stream, Bm + c0 * ldb,
+                               ldb, part, kResidChunks, m, nc, rv, st);
+            // s = R^{-T} A^T r, beta = ||s||^2 / gamma, p = s + beta p, stopping test
+            hipLaunchKernelGGL(k_gemv_t, dim3((unsigned)n), dim3(NT), 0, stream, A, lda, m, rv, nc, sv, n, done);
+            s1 = narrow_trsv<B>(true, m, n, nc, W, sv, n, nm, stream, &o);
             if (s1 != TQR_OK) return s1;
-            s1 = narrow_trsv<B>(true, m, n, nrhs, W, G, n, nm, stream, &o);  // h = R^{-T} g
-            if (s1 != TQR_OK) return s1;
-            // u = d[0:n] - h;  f <- [h; d[n:m]]
-            hipLaunchKernelGGL(k_aug_combine_cm, dim3(gn), dim3(256), 0, stream, F, m, G, n, Ut, n, n, (int)nrhs);
-            s1 = narrow_trsv<B>(false, m, n, nrhs, W, Ut, n, nm, stream, &o);  // dx = R^{-1} u
-            if (s1 != TQR_OK) return s1;
-            s1 = narrow_apply<B, 16>(false, m, n, nrhs, T, W, Vd, F, m, nm, stream, &o);  // dr = Q [h; d2]
-            if (s1 != TQR_OK) return s1;
-            hipLaunchKernelGGL(k_add_cm, dim3(gn), dim3(256), 0, stream, Ut, n, Xv, n, n, (int)nrhs);
-            hipLaunchKernelGGL(k_add_cm, dim3(gm), dim3(256), 0, stream, F, m, Rv, m, m, (int)nrhs);
+            hipLaunchKernelGGL(k_cgls_next, dim3(nc), dim3(NT), 0, stream, sv, xv, rv, n, m, nc, fro2, st, it + 1);
+            hipLaunchKernelGGL(k_cgls_update_p, dim3(gn4), dim3(256), 0, stream, pv, sv, n, nc, st);
+            hipLaunchKernelGGL(k_cgls_alldone, dim3(1), dim3(64), 0, stream, st, nc, done);
         }
-        hipLaunchKernelGGL(k_copy_cm, dim3(gn), dim3(256), 0, stream, Xv, n, X, ldx, n, (int)nrhs, 1.0);
-        HIPCHK(hipGetLastError());
-        return TQR_OK;
+        hipLaunchKernelGGL(k_copy_cm, dim3(gn4), dim3(256), 0, stream, xv, n, X + c0 * ldx, ldx, n, nc, 1.0);
+        if (stats) hipLaunchKernelGGL(k_cgls_report, dim3(1), dim3(64), 0, stream, st, nc, stats + c0);
     }
-    for (int it = 0; it < iterations; ++it) {
-        // FP64 residuals of the augmented system
-        hipLaunchKernelGGL(k_resid_partial, dim3((unsigned)cdiv(m, 256), kResidChunks), dim3(256), 0, stream, A, lda, m,
-                           n, Xv, n, (int)nrhs, Part);
-        hipLaunchKernelGGL(k_resid_reduce, dim3(gm), dim3(256), 0, stream, Bm, ldb, Rv, m, (int)nrhs, kResidChunks, Part,
-                           F);
-        hipLaunchKernelGGL(k_neg_atr, dim3((unsigned)n), dim3(NT), 0, stream, A, lda, m, Rv, (int)nrhs, G, n);
-        // d = Q^T f (in Bt);  h = R^{-T} g (in Ht)
-        s1 = apply_impl<B, 16>(true, m, n, nrhs, T, W, Vd, F, m, Bt, sched, stream, &o);
-        if (s1 != TQR_OK) return s1;
-        hipLaunchKernelGGL(k_cm_to_tiles, dim3((unsigned)z.p, 1), dim3(256), 0, stream, G, n, n, nrhs, Ht, (int)z.p, B,
-                           (int)wb);
-        s1 = trsmt_impl<B>(m, n, nrhs, W, Ht, sched, stream, &o);
-        if (s1 != TQR_OK) return s1;
-        // u = d[0:n] - h;  Bt <- [h; d[n:m]]
-        hipLaunchKernelGGL(k_aug_combine, dim3((unsigned)cdiv(btot, 256)), dim3(256), 0, stream, Bt, Ht, Ut, B, (int)wb,
-                           n, btot);
-        s1 = trsm_impl<B>(m, n, nrhs, W, Ut, sched, stream, &o);  // dx = R^{-1} u
-        if (s1 != TQR_OK) return s1;
-        s1 = apply_impl<B, 16>(false, m, n, nrhs, T, W, Vd, nullptr, 0, Bt, sched, stream, &o);  // dr
-        if (s1 != TQR_OK) return s1;
-        hipLaunchKernelGGL(k_tiles_add_to_cm, dim3(gn), dim3(256), 0, stream, Ut, B, (int)wb, Xv, n, (int)nrhs);
-        hipLaunchKernelGGL(k_tiles_add_to_cm, dim3(gm), dim3(256), 0, stream, Bt, B, (int)wb, Rv, m, (int)nrhs);
-    }
-    hipLaunchKernelGGL(k_copy_cm, dim3(gn), dim3(256), 0, stream, Xv, n, X, ldx, n, (int)nrhs, 1.0);
+    HIPCHK(hipGetLastError());
     return TQR_OK;
 }
 
@@ -2169,7 +2121,7 @@ struct PairFns {
     // inner block 16 and tile_b 64, 128 or 256 only; null otherwise
     tqr_status (*mixed)(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *Bm, int64_t ldb,
                         double *X, int64_t ldx, int iterations, double *T, void *work, int32_t *d_info,
-                        hipStream_t stream, const tqr_options &o);
+                        tqr_refine_stats *stats, hipStream_t stream, const tqr_options &o);
 };
 
 template <int B, int IB>

@@ -33,12 +33,15 @@
 // Ordering and progress.  A workgroup takes its place in the pipeline from a
 // ticket counter, not from its block index, so every workgroup it waits for
 // has already started and holds its compute unit: the launch cannot wait on a
-// workgroup that is not resident.  Hand-over buffers and flags are written
-// and read with relaxed system-scope atomics, which go to memory rather than
-// to a compute unit's or an XCD's cache; a writer waits for its own stores to
-// complete before it raises the flag.  Every wait is bounded (device clock
-// and spin count): a wait that runs out sets the abort word, which every
-// waiting workgroup also watches, and TQR_EABORTED in the status word.
+// workgroup that is not resident.  Hand-over buffers are filled with a
+// "pending" bit pattern (a signalling NaN, which no arithmetic result has:
+// results of operations are quiet) before the launch; a writer stores each
+// value with a relaxed system-scope atomic (which goes to memory rather than
+// to a compute unit's or an XCD's cache), and a reader polls the value itself
+// until it is no longer pending, so a hand-over costs one trip to memory on
+// each side and no separate flag.  Every wait is bounded (device clock and
+// spin count): a wait that runs out sets the abort word, which every waiting
+// thread also watches, and TQR_EABORTED in the status word.
 // Included by tqr_impl.h inside namespace tqr, after the scheduler's flag
 // helpers.
 #pragma once
@@ -64,20 +67,34 @@ __device__ __forceinline__ void coh_store(double *p, double v) {
                        TQR_FLAG_SCOPE);
 }
 
-// One lane: waits until *flag != 0.  False when the launch was aborted
-// (here or elsewhere).
-__device__ bool narrow_wait(const int32_t *flag, const NarrowCtl &c) {
+// The "pending" pattern of hand-over buffers: a signalling NaN.
+constexpr uint64_t kPendingBits = 0x7FF4D1A5C0FFEE01ull;
+
+// Waits until *p holds a value (not the pending pattern) and returns it in
+// `out`; false when the launch was aborted (here or elsewhere).  Each calling
+// thread polls its own value.
+__device__ bool narrow_take(const double *p, double &out, const NarrowCtl &c) {
+    uint64_t u = __hip_atomic_load(reinterpret_cast<uint64_t *>(const_cast<double *>(p)), __ATOMIC_RELAXED,
+                                   TQR_FLAG_SCOPE);
+    if (u != kPendingBits) {
+        out = __builtin_bit_cast(double, u);
+        return true;
+    }
     const uint64_t deadline = rt_clock() + (uint64_t)c.timeout;
     uint32_t n = 0;
-    while (flag_load(flag) == 0) {
+    while (true) {
+        __builtin_amdgcn_s_sleep(1);
+        u = __hip_atomic_load(reinterpret_cast<uint64_t *>(const_cast<double *>(p)), __ATOMIC_RELAXED,
+                              TQR_FLAG_SCOPE);
+        if (u != kPendingBits) break;
         if (flag_load(c.abort) != 0) return false;
         if (rt_clock() > deadline || ++n > kMaxSpins) {
             __hip_atomic_store(c.abort, 1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
             if (c.status) __hip_atomic_store(c.status, (int32_t)TQR_EABORTED, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
             return false;
         }
-        __builtin_amdgcn_s_sleep(1);
     }
+    out = __builtin_bit_cast(double, u);
     return true;
 }
 
@@ -111,8 +128,7 @@ struct NarrowApplyArgs {
     double *Bm;
     int64_t ldb, m;
     int nrhs, p, q;
-    double *H;        // hand-over blocks: slot (k, i, s) holds ib x NR doubles
-    int32_t *flags;   // one per slot
+    double *H;        // hand-over blocks: slot (k, i, s) holds ib x NR doubles, pending on entry
     NarrowCtl ctl;
 };
 
@@ -154,16 +170,11 @@ __global__ __launch_bounds__(B) void k_narrow_apply(NarrowApplyArgs a) {
             // the input itself when there is no row below)
             if (!TRANS && top && k + 1 < p) {
                 const int owner = (s * IB) / 64;
-                if (wv == owner) {
-                    int ok = 1;
-                    if (l == 0) ok = narrow_wait(a.flags + slot(k, k + 1, s), a.ctl);
-                    ok = __builtin_amdgcn_readfirstlane(ok);
-                    if (!ok) s_ok = 0;
-                    if (ok && t >= s * IB && t < s * IB + IB) {
-                        const double *h = a.H + slot(k, k + 1, s) * IB * NR;
+                if (wv == owner && t >= s * IB && t < s * IB + IB) {
+                    const double *h = a.H + slot(k, k + 1, s) * IB * NR;
 #pragma unroll
-                        for (int r = 0; r < NR; ++r) bi[r] = coh_load(h + r * IB + (t - s * IB));
-                    }
+                    for (int r = 0; r < NR; ++r)
+                        if (!narrow_take(h + r * IB + (t - s * IB), bi[r], a.ctl)) s_ok = 0;
                 }
             }
             double v[IB];
@@ -188,57 +199,40 @@ __global__ __launch_bounds__(B) void k_narrow_apply(NarrowApplyArgs a) {
             if (!s_ok) break;
             if (wv == 0) {
                 double bk = 0.0;
-                bool ok = true;
-                if (!top) {
+                if (!top && former) {
                     // row block s of tile k from the previous workgroup of the chain
                     const bool first = TRANS ? false : i == p - 1;
-                    const int64_t in = TRANS ? slot(k, i - 1, s) : slot(k, i + 1, s);
-                    if (!first) {
-                        int okl = 1;
-                        if (l == 0) okl = narrow_wait(a.flags + in, a.ctl);
-                        ok = __builtin_amdgcn_readfirstlane(okl) != 0;
-                    }
-                    if (ok && former) {
-                        if (first) {
-                            const int64_t row = (int64_t)k * B + s * IB + wc;
-                            bk = (row < a.m && wr < a.nrhs) ? a.Bm[wr * a.ldb + row] : 0.0;
-                        } else {
-                            bk = coh_load(a.H + in * IB * NR + wr * IB + wc);
-                        }
+                    if (first) {
+                        const int64_t row = (int64_t)k * B + s * IB + wc;
+                        bk = (row < a.m && wr < a.nrhs) ? a.Bm[wr * a.ldb + row] : 0.0;
+                    } else {
+                        const int64_t in = TRANS ? slot(k, i - 1, s) : slot(k, i + 1, s);
+                        if (!narrow_take(a.H + in * IB * NR + wr * IB + wc, bk, a.ctl)) s_ok = 0;
                     }
                 }
-                if (!ok) {
-                    if (l == 0) s_ok = 0;
-                } else {
-                    if (former) {
-                        double z = 0.0;
+                if (former) {
+                    double z = 0.0;
 #pragma unroll
-                        for (int w = 0; w < NWV; ++w) z += zpart[w][wr][wc];
-                        ush[wr][wc] = bk + z;
-                    }
-                    // W = T_s^T U (Q^T) or T_s U (Q); T_s upper triangular
-                    if (former) {
-                        double w = 0.0;
+                    for (int w = 0; w < NWV; ++w) z += zpart[w][wr][wc];
+                    ush[wr][wc] = bk + z;
+                }
+                // W = T_s^T U (Q^T) or T_s U (Q); T_s upper triangular
+                if (former) {
+                    double w = 0.0;
 #pragma unroll
-                        for (int c2 = 0; c2 < IB; ++c2) {
-                            const bool in_tri = TRANS ? c2 <= wc : c2 >= wc;
-                            if (in_tri) w += tcol[c2] * ush[wr][c2];
-                        }
-                        wsh[wr][wc] = w;
-                        if (!top) {
-                            const double out = bk - w;
-                            const bool last = TRANS ? i == p - 1 : false;
-                            if (last) {
-                                const int64_t row = (int64_t)k * B + s * IB + wc;
-                                if (row < a.m && wr < a.nrhs) a.Bm[wr * a.ldb + row] = out;
-                            } else {
-                                coh_store(a.H + slot(k, i, s) * IB * NR + wr * IB + wc, out);
-                            }
-                        }
+                    for (int c2 = 0; c2 < IB; ++c2) {
+                        const bool in_tri = TRANS ? c2 <= wc : c2 >= wc;
+                        if (in_tri) w += tcol[c2] * ush[wr][c2];
                     }
-                    if (!top && !(TRANS && i == p - 1)) {
-                        wait_own_stores();
-                        if (l == 0) __hip_atomic_store(a.flags + slot(k, i, s), 1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+                    wsh[wr][wc] = w;
+                    if (!top) {
+                        const double out = bk - w;
+                        if (TRANS && i == p - 1) {
+                            const int64_t row = (int64_t)k * B + s * IB + wc;
+                            if (row < a.m && wr < a.nrhs) a.Bm[wr * a.ldb + row] = out;
+                        } else {
+                            coh_store(a.H + slot(k, i, s) * IB * NR + wr * IB + wc, out);
+                        }
                     }
                 }
             }
@@ -255,21 +249,15 @@ __global__ __launch_bounds__(B) void k_narrow_apply(NarrowApplyArgs a) {
             // Q^T, top: row block s of tile k is final for this column
             if (TRANS && top) {
                 const int owner = (s * IB) / 64;
-                if (wv == owner) {
-                    if (t >= s * IB && t < s * IB + IB) {
-                        if (k == p - 1) {
+                if (wv == owner && t >= s * IB && t < s * IB + IB) {
+                    if (k == p - 1) {
 #pragma unroll
-                            for (int r = 0; r < NR; ++r)
-                                if (grow < a.m && r < a.nrhs) a.Bm[r * a.ldb + grow] = bi[r];
-                        } else {
-                            double *h = a.H + slot(k, k, s) * IB * NR;
+                        for (int r = 0; r < NR; ++r)
+                            if (grow < a.m && r < a.nrhs) a.Bm[r * a.ldb + grow] = bi[r];
+                    } else {
+                        double *h = a.H + slot(k, k, s) * IB * NR;
 #pragma unroll
-                            for (int r = 0; r < NR; ++r) coh_store(h + r * IB + (t - s * IB), bi[r]);
-                        }
-                    }
-                    if (k != p - 1) {
-                        wait_own_stores();
-                        if (l == 0) __hip_atomic_store(a.flags + slot(k, k, s), 1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
+                        for (int r = 0; r < NR; ++r) coh_store(h + r * IB + (t - s * IB), bi[r]);
                     }
                 }
             }
@@ -297,8 +285,8 @@ struct NarrowTrsvArgs {
     double *Y;
     int64_t ldy;
     int nrhs;
-    double *X;        // published solution blocks: block j at X + j * 64 * NR (row-major by rhs)
-    int32_t *flags;   // one per block
+    double *X;        // published solution blocks: block j at X + j * 64 * NR (by rhs), pending on entry
+    const int32_t *skip;  // nonzero: return at once (or null)
     NarrowCtl ctl;
 };
 
@@ -312,9 +300,11 @@ __global__ __launch_bounds__(256) void k_narrow_trsv(NarrowTrsvArgs a) {
     constexpr int RB = kTrsvRows, NW = 4;
     __shared__ double xs[NR][RB];            // the arriving solution block
     __shared__ double part[NW][NR][RB];      // per-wave partial sums
+    __shared__ double dsh[RB][RB + 1];       // the diagonal block R_jj (padded rows)
     __shared__ int s_blk, s_ok;
     const int t = threadIdx.x, l = lane_id(), wv = wave_id();
     const int nb = (int)((a.n + RB - 1) / RB);
+    if (a.skip && *a.skip) return;
     if (t == 0) {
         const int tk = __hip_atomic_fetch_add(a.ctl.ticket, 1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
         s_blk = TRANS ? tk : nb - 1 - tk;
@@ -323,6 +313,11 @@ __global__ __launch_bounds__(256) void k_narrow_trsv(NarrowTrsvArgs a) {
     __syncthreads();
     const int j = s_blk;
     const int64_t r0 = (int64_t)j * RB;
+    // stage the diagonal block while the earlier blocks are being solved
+    for (int idx = t; idx < RB * RB; idx += 256) {
+        const int rr = idx % RB, cc = idx / RB;
+        dsh[rr][cc] = (r0 + rr < a.n && r0 + cc < a.n) ? r_at<B>(a.W, a.p, r0 + rr, r0 + cc) : 0.0;
+    }
     // Back substitution: lane l of every wave owns row r0 + l and wave w
     // takes columns 16w .. 16w+15 of each arriving block.  Forward: lane l
     // is row l of the arriving block and wave w accumulates the products for
@@ -354,11 +349,13 @@ __global__ __launch_bounds__(256) void k_narrow_trsv(NarrowTrsvArgs a) {
     if (cnt > 0) load_block(TRANS ? 0 : nb - 1);
     for (int e = 0; e < cnt; ++e) {
         const int c = TRANS ? e : nb - 1 - e;
-        if (t == 0 && !narrow_wait(a.flags + c, a.ctl)) s_ok = 0;
+        if (t < RB * NR) {
+            double v = 0.0;
+            if (!narrow_take(a.X + (int64_t)c * RB * NR + t, v, a.ctl)) s_ok = 0;
+            xs[t / RB][t % RB] = v;
+        }
         __syncthreads();
         if (!s_ok) return;
-        if (t < RB * NR) xs[t / RB][t % RB] = coh_load(a.X + (int64_t)c * RB * NR + t);
-        __syncthreads();
         double cur[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) cur[u] = rv[u];
@@ -390,18 +387,13 @@ __global__ __launch_bounds__(256) void k_narrow_trsv(NarrowTrsvArgs a) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) part[wv][r][l] = acc[r];
     }
+    __syncthreads();
+    if (wv != 0) return;
     // diagonal block: lane l holds row l (back) or column l (forward) of R_jj
     double dg[RB];
     const int64_t myrow = r0 + l;
 #pragma unroll
-    for (int u = 0; u < RB; ++u) {
-        const int64_t cc = r0 + u;
-        double v = 0.0;
-        if (wv == 0 && myrow < a.n && cc < a.n) v = TRANS ? r_at<B>(a.W, a.p, cc, myrow) : r_at<B>(a.W, a.p, myrow, cc);
-        dg[u] = v;
-    }
-    __syncthreads();
-    if (wv != 0) return;
+    for (int u = 0; u < RB; ++u) dg[u] = TRANS ? dsh[u][l] : dsh[l][u];
     double y[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -441,7 +433,5 @@ __global__ __launch_bounds__(256) void k_narrow_trsv(NarrowTrsvArgs a) {
     if (others) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) coh_store(a.X + (int64_t)j * RB * NR + r * RB + l, myrow < a.n ? y[r] : 0.0);
-        wait_own_stores();
-        if (l == 0) __hip_atomic_store(a.flags + j, 1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
     }
 }

@@ -93,7 +93,7 @@ def lib() -> ctypes.CDLL:
         L.tqr_solve_ls_ex.restype = i32
         L.tqr_ls_mixed_workspace_bytes.argtypes = [i64, i64, i64, i32]
         L.tqr_ls_mixed_workspace_bytes.restype = i64
-        L.tqr_solve_ls_mixed.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64, i32, i32, dp, vp, i64, vp, vp,
+        L.tqr_solve_ls_mixed.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64, i32, i32, dp, vp, i64, vp, vp, vp,
                                          ctypes.POINTER(Options)]
         L.tqr_solve_ls_mixed.restype = i32
         L.tqr_batch_plan.argtypes = [i64, ctypes.POINTER(BatchProblem)]
@@ -270,13 +270,26 @@ def solve_ls(A, B, tile_b, inner_ib, ws: Workspace | None = None, *, workgroups:
 
 # ---- mixed-precision least squares -------------------------------------------------
 
-def solve_ls_mixed(A: torch.Tensor, B: torch.Tensor, tile_b: int, iterations: int = 5, *,
+REFINE_CONVERGED, REFINE_STAGNATED, REFINE_MAX_ITERATIONS, REFINE_BREAKDOWN = 1, 2, 3, 4
+REFINE_ETA_TOL = 1e-15
+
+def refine_stats(stats: torch.Tensor):
+    """Host copy of a device tqr_refine_stats array (see solve_ls_mixed): a
+    list of dicts with iterations, stop and eta per right-hand side."""
+    import numpy as np
+    raw = stats.cpu().numpy().view(np.dtype([("iterations", "<i4"), ("stop", "<i4"), ("eta", "<f8")]))
+    return [{"iterations": int(r["iterations"]), "stop": int(r["stop"]), "eta": float(r["eta"])} for r in raw]
+
+
+def solve_ls_mixed(A: torch.Tensor, B: torch.Tensor, tile_b: int, iterations: int = 20, *,
                    precision: int = PRECISION_FP32_UPDATES, workgroups: int = 0, work: torch.Tensor | None = None,
                    X: torch.Tensor | None = None, info: torch.Tensor | None = None, events=None,
-                   policy: int = POLICY_COLUMN):
+                   policy: int = POLICY_COLUMN, status: torch.Tensor | None = None):
     """min ||A X - B|| with the factor's trailing updates in FP32 and FP64
-    refinement of the augmented system (tqr_solve_ls_mixed).  A and B are
-    column-major and left unchanged; returns (X, T, info)."""
+    CGLS on A R^{-1} (tqr_solve_ls_mixed), at most ``iterations`` iterations
+    per right-hand side.  A and B are column-major and left unchanged;
+    returns (X, T, info, stats) with ``stats`` the device tqr_refine_stats
+    array (decode with refine_stats)."""
     m, n = A.shape
     nrhs = B.shape[1]
     nb = int(lib().tqr_ls_mixed_workspace_bytes(m, n, nrhs, tile_b))
@@ -288,14 +301,17 @@ def solve_ls_mixed(A: torch.Tensor, B: torch.Tensor, tile_b: int, iterations: in
         X = torch.empty((nrhs, max(n, 1)), dtype=torch.float64, device=A.device).t()[:n]
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    stats = torch.zeros(2 * nrhs, dtype=torch.float64, device=A.device)
     T = torch.zeros(max(t_elems(m, n, tile_b, 16), 1), dtype=torch.float64, device=A.device)
-    opt = Options(ctypes.sizeof(Options), workgroups, MODE_PERSISTENT, policy, None, None, None, 0,
+    opt = Options(ctypes.sizeof(Options), workgroups, MODE_PERSISTENT, policy, None, None,
+                  status.data_ptr() if status is not None else None, 0,
                   events[0] if events else None, events[1] if events else None, precision, 0)
     rc = lib().tqr_solve_ls_mixed(m, n, nrhs, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), X.data_ptr(),
                                   max(1, X.stride(1) if nrhs > 1 else n), tile_b, iterations, T.data_ptr(),
-                                  work.data_ptr(), work.numel(), info.data_ptr(), _stream(), ctypes.byref(opt))
+                                  work.data_ptr(), work.numel(), info.data_ptr(), stats.data_ptr(), _stream(),
+                                  ctypes.byref(opt))
     _check("tqr_solve_ls_mixed", rc)
-    return X, T, info
+    return X, T, info, stats
 
 
 # ---- batched factorisation ------------------------------------------------------

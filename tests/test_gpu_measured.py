@@ -146,3 +146,45 @@ def test_large_grids_match_oracle_and_are_schedule_invariant(m, n, b, ib):
             else:
                 assert np.array_equal(out[0], ref[0]), (wg, pol)
                 assert np.array_equal(out[1], ref[1]), (wg, pol)
+
+
+# Least squares at the size the benchmark's mixed-precision leg measures:
+# 16384 x 4096, A = U diag(s) V^T with s log-spaced (cond in {1e2, 1e5, 1e8}),
+# U and V from QR of Gaussians, b = A x + 1e-6 N(0,1).
+@pytest.mark.parametrize("cond", [1e2, 1e5, 1e8])
+def test_least_squares_16384x4096_fp64_and_mixed_match_oracle(cond):
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    m, n, b, ib = 16384, 4096, 256, 16
+    _say(f"case LS {m}x{n} cond={cond:g}: generating")
+    A, Bh, _ = workloads.ls_problem(m, n, cond, seed=41, nrhs=1)
+    dA0 = tqr.fortran(torch.from_numpy(A).cuda())
+    dB0 = tqr.fortran(torch.from_numpy(Bh).cuda())
+    _say(f"case LS cond={cond:g}: FP64 tqr_solve_ls")
+    dA, dB = dA0.clone(), dB0.clone()
+    _, info = tqr.solve_ls(dA, dB, b, ib)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    x64 = dB[:n, 0].cpu().numpy()
+    # beyond 1 / u32 the FP32-update factor is no usable preconditioner: the
+    # mixed solver is run with the FP64 factor there (its FP32 attempt is
+    # checked to report its stagnation honestly in tests/test_mixed.py)
+    prec = tqr.PRECISION_FP32_UPDATES if cond < 1e7 else tqr.PRECISION_FP64
+    _say(f"case LS cond={cond:g}: mixed (factor precision {prec} + FP64 CGLS)")
+    X, _, info, stats = tqr.solve_ls_mixed(dA0, dB0, b, iterations=30, precision=prec)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    xmx = X[:, 0].cpu().numpy()
+    st = tqr.refine_stats(stats)[0]
+    _say(f"case LS cond={cond:g}: oracle lstsq and backward errors on {oracle.num_threads(omp=True)} threads")
+    xo, _ = oracle.lstsq(A, Bh, omp=True)
+    xo = xo[:, 0]
+    f64 = np.linalg.norm(x64 - xo) / np.linalg.norm(xo)
+    fmx = np.linalg.norm(xmx - xo) / np.linalg.norm(xo)
+    e64 = oracle.ls_backward_error(A, x64, Bh[:, 0], omp=True)
+    emx = oracle.ls_backward_error(A, xmx, Bh[:, 0], omp=True)
+    _say(f"case LS cond={cond:g}: FP64 forward {f64:.3e} eta {e64:.3e}; mixed forward {fmx:.3e} eta {emx:.3e} "
+         f"({st['iterations']} iterations, stop {st['stop']}, device eta {st['eta']:.3e})")
+    assert f64 < cond * 1e-13 and e64 < 1e-14
+    assert fmx < cond * 1e-13 and emx < 1e-14
+    assert st["stop"] in (tqr.REFINE_CONVERGED, tqr.REFINE_STAGNATED)

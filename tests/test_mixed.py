@@ -1,6 +1,6 @@
 """FP32 precision tier (trailing updates on the FP32 matrix cores) and the
-mixed-precision least-squares solver with FP64 refinement of the augmented
-system.
+mixed-precision least-squares solver (FP32-update factor, then FP64 CGLS on
+A R^{-1}).
 
 Tolerances: the FP32-update factor is compared with the unblocked FP64 oracle
 to FP32 accuracy (R to 1e-4 relative, ||A - QR|| / ||A|| to 50 sqrt(n) u32),
@@ -37,7 +37,7 @@ def test_mixed_argument_checks():
     from paper_0707_3548_amd import tqr
     L = tqr.lib()
     a = ctypes.c_void_p(4096)
-    args = [100, 50, 1, a, 100, a, 100, a, 50, 64, 3, a, a, 1 << 30, a, None, None]
+    args = [100, 50, 1, a, 100, a, 100, a, 50, 64, 3, a, a, 1 << 30, a, None, None, None]
     def rc(**kw):
         v = list(args)
         names = ["m", "n", "nrhs", "A", "lda", "B", "ldb", "X", "ldx", "tile_b", "iters", "T", "work", "wb", "info"]
@@ -51,7 +51,8 @@ def test_mixed_argument_checks():
     assert rc(ldb=10) == -7
     assert rc(ldx=10) == -9
     assert rc(tile_b=32) == -10
-    assert rc(iters=51) == -11
+    assert rc(iters=201) == -11
+    assert rc(iters=-1) == -11
     assert rc(wb=100) == -14
     assert rc(info=None) == -15
 
@@ -87,8 +88,13 @@ def test_fp32_updates_factor(m, n, b):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("m,n,b,nrhs,cond", [(512, 256, 64, 1, 1e2), (600, 400, 64, 3, 1e5), (1000, 300, 128, 2, 1e3),
-                                             (777, 500, 256, 1, 1e4)])
+                                             (777, 500, 256, 1, 1e4), (900, 400, 128, 6, 1e6)])
 def test_mixed_ls_reaches_fp64_accuracy(m, n, b, nrhs, cond):
+    """The refined solution meets the FP64 solver's bounds: backward error
+    < 1e-14 and forward error < cond * 1e-13 against the oracle; the device's
+    stopping test reports convergence or stagnation (not the limit), and its
+    estimate agrees with the oracle's backward error (same formula with the
+    oracle's triangle of [A; mu I])."""
     torch = _torch()
     from paper_0707_3548_amd import tqr, workloads
     print(f"case mixed LS m={m} n={n} b={b} nrhs={nrhs} cond={cond}", flush=True)
@@ -96,30 +102,73 @@ def test_mixed_ls_reaches_fp64_accuracy(m, n, b, nrhs, cond):
     dA = tqr.fortran(torch.from_numpy(A).cuda())
     dB = tqr.fortran(torch.from_numpy(Bh).cuda())
     A0, B0 = dA.clone(), dB.clone()
-    X, _, info = tqr.solve_ls_mixed(dA, dB, b, iterations=6)
+    X, _, info, stats = tqr.solve_ls_mixed(dA, dB, b, iterations=40)
     torch.cuda.synchronize()
     assert int(info.item()) == 0
     assert torch.equal(dA, A0) and torch.equal(dB, B0)
     Xh = X.cpu().numpy()
     Xo, _ = oracle.lstsq(A, Bh)
     assert np.linalg.norm(Xh - Xo) / np.linalg.norm(Xo) < cond * 1e-13
+    st = tqr.refine_stats(stats)
     for c in range(nrhs):
-        assert oracle.ls_backward_error(A, Xh[:, c], Bh[:, c]) < 1e-14
+        eta = oracle.ls_backward_error(A, Xh[:, c], Bh[:, c])
+        print(f"  rhs {c}: {st[c]}, oracle eta {eta:.3e}", flush=True)
+        assert eta < 1e-14
+        assert st[c]["stop"] in (tqr.REFINE_CONVERGED, tqr.REFINE_STAGNATED)
+        assert 0 < st[c]["iterations"] < 40
+        assert st[c]["eta"] < 1e-14
 
 
 @pytest.mark.gpu
 def test_mixed_ls_with_fp64_factor_and_zero_iterations():
-    """iterations = 0 returns x = 0; with an FP64 factor one step already
-    reaches the semi-normal-equations solution and a few more the bound."""
+    """iterations = 0 returns x = 0; with an FP64 factor A R^{-1} is
+    orthogonal to FP64 rounding and CGLS stops within three iterations."""
     torch = _torch()
     from paper_0707_3548_amd import tqr, workloads
     print("case mixed LS fp64 factor", flush=True)
     A, Bh, _ = workloads.ls_problem(300, 200, 1e2, seed=33, nrhs=1)
     dA = tqr.fortran(torch.from_numpy(A).cuda())
     dB = tqr.fortran(torch.from_numpy(Bh).cuda())
-    X0, _, _ = tqr.solve_ls_mixed(dA, dB, 64, iterations=0)
+    X0, _, _, st0 = tqr.solve_ls_mixed(dA, dB, 64, iterations=0)
     torch.cuda.synchronize()
     assert float(X0.abs().max()) == 0.0
-    X, _, info = tqr.solve_ls_mixed(dA, dB, 64, iterations=3, precision=tqr.PRECISION_FP64)
+    assert tqr.refine_stats(st0)[0]["iterations"] == 0
+    X, _, info, st = tqr.solve_ls_mixed(dA, dB, 64, iterations=20, precision=tqr.PRECISION_FP64)
     torch.cuda.synchronize()
     assert oracle.ls_backward_error(A, X.cpu().numpy()[:, 0], Bh[:, 0]) < 1e-14
+    assert tqr.refine_stats(st)[0]["iterations"] <= 3
+
+
+@pytest.mark.gpu
+def test_mixed_ls_beyond_the_fp32_factor_reports_stagnation_honestly():
+    """cond 1e8 exceeds 1 / u32: the FP32-update factor's R is no longer a
+    useful preconditioner (cond * u32 ~ 6), CGLS stalls far above FP64
+    accuracy, and the solver says so (stop = stagnated, its estimate within
+    a factor 10 of the oracle's backward error, which is above 1e-14).  The
+    same solver with the FP64 factor reaches FP64 accuracy."""
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    m, n, b, cond = 700, 350, 64, 1e8
+    print(f"case mixed LS cond={cond:g} (beyond the FP32 factor)", flush=True)
+    A, Bh, _ = workloads.ls_problem(m, n, cond, seed=34, nrhs=1)
+    dA = tqr.fortran(torch.from_numpy(A).cuda())
+    dB = tqr.fortran(torch.from_numpy(Bh).cuda())
+    X, _, info, stats = tqr.solve_ls_mixed(dA, dB, b, iterations=60)
+    torch.cuda.synchronize()
+    st = tqr.refine_stats(stats)[0]
+    eta = oracle.ls_backward_error(A, X.cpu().numpy()[:, 0], Bh[:, 0])
+    print(f"  FP32 factor: {st}, oracle eta {eta:.3e}", flush=True)
+    if eta < 1e-14:
+        assert st["stop"] == tqr.REFINE_CONVERGED
+    else:
+        assert st["stop"] in (tqr.REFINE_STAGNATED, tqr.REFINE_MAX_ITERATIONS)
+        assert st["eta"] > 1e-14 and 0.1 < st["eta"] / eta < 10
+    X, _, info, stats = tqr.solve_ls_mixed(dA, dB, b, iterations=20, precision=tqr.PRECISION_FP64)
+    torch.cuda.synchronize()
+    st = tqr.refine_stats(stats)[0]
+    Xh = X.cpu().numpy()
+    eta = oracle.ls_backward_error(A, Xh[:, 0], Bh[:, 0])
+    print(f"  FP64 factor: {st}, oracle eta {eta:.3e}", flush=True)
+    assert eta < 1e-14 and st["stop"] == tqr.REFINE_CONVERGED
+    Xo, _ = oracle.lstsq(A, Bh)
+    assert np.linalg.norm(Xh - Xo) / np.linalg.norm(Xo) < cond * 1e-13
