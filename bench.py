@@ -329,51 +329,54 @@ def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
 def batched_leg(count: int, steps: int = 5):
     """The batched factorisation: ``count`` independent N(0,1) problems, m
     log-uniform in [16, 512], n uniform in [8, m], one launch per batch
-    (tile size per problem from the size-bucket table), inputs already in
-    HBM; timed eagerly (HIP events around the launch, the inputs restored by
-    a device copy outside) and as a replayed graph."""
+    ((tile_b, inner_ib) per problem from the tuned size-bucket table), FP64
+    and FP32-update variants, inputs already in HBM; timed eagerly (HIP
+    events around the launch, the inputs restored by a device copy outside)
+    and as a replayed graph."""
     import torch
     from paper_0707_3548_amd import autotune, tqr, workloads
 
     shapes = workloads.batch_shapes(count, seed=11)
-    table = autotune.current_table()
-    tiles = [autotune.tile_for(n, table) for _, n in shapes]
-    bt = tqr.Batch(shapes, tiles)
-    workloads.fill_normal_device(bt.A, 12)
-    pristine = bt.A.clone()
     flops = sum(2.0 * n * n * (m - n / 3.0) for m, n in shapes)
-
-    def timed(run):
-        ts = []
-        for s in range(steps + 1):
-            bt.A.copy_(pristine)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            run()
-            e1.record()
-            torch.cuda.synchronize()
-            if s > 0:
-                ts.append(e0.elapsed_time(e1))
-        return sorted(ts)[len(ts) // 2]
-
-    eager_ms = timed(bt.factor)
-    g = torch.cuda.CUDAGraph()
-    st = torch.cuda.Stream()
-    bt.A.copy_(pristine)
-    torch.cuda.synchronize()
-    with torch.cuda.graph(g, stream=st):
-        bt.factor()
-    graph_ms = timed(g.replay)
-    ok = int(bt.status.item()) == 0
     out = {"workload": f"{count} independent N(0,1) QRs, m log-uniform [16, 512], n uniform [8, m], one launch, "
-                       "one workgroup per problem, tile size per bucket of n",
-           "problems": count, "tile_table": [list(e) for e in table], "gflop_standard": round(flops / 1e9, 2),
-           "ms_per_batch": round(eager_ms, 3), "ms_per_batch_graph": round(graph_ms, 3),
-           "problems_per_s": round(count / (eager_ms / 1e3), 1), "gflops_standard": round(flops / eager_ms / 1e6, 1),
-           "status_ok": ok}
-    print(f"bench: batched {count} problems: {eager_ms:.2f} ms eager, {graph_ms:.2f} ms graph", file=sys.stderr, flush=True)
-    del bt, pristine
-    torch.cuda.empty_cache()
+                       "one workgroup per problem, (tile_b, inner_ib) per bucket of n from the autotuner",
+           "problems": count, "gflop_standard": round(flops / 1e9, 2)}
+    for name, prec in (("fp64", tqr.PRECISION_FP64), ("fp32_updates", tqr.PRECISION_FP32_UPDATES)):
+        table = autotune.current_table("fp64" if name == "fp64" else "fp32")
+        tilings = [autotune.tiling_for(n, table) for _, n in shapes]
+        bt = tqr.Batch(shapes, [t[0] for t in tilings], [t[1] for t in tilings], precision=prec)
+        workloads.fill_normal_device(bt.A, 12)
+        pristine = bt.A.clone()
+
+        def timed(run):
+            ts = []
+            for s in range(steps + 1):
+                bt.A.copy_(pristine)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                run()
+                e1.record()
+                torch.cuda.synchronize()
+                if s > 0:
+                    ts.append(e0.elapsed_time(e1))
+            return sorted(ts)[len(ts) // 2]
+
+        eager_ms = timed(bt.factor)
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        bt.A.copy_(pristine)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=st):
+            bt.factor()
+        graph_ms = timed(g.replay)
+        ok = int(bt.status.item()) == 0
+        out[name] = {"tile_table": [list(e) for e in table], "ms_per_batch": round(eager_ms, 3),
+                     "ms_per_batch_graph": round(graph_ms, 3), "problems_per_s": round(count / (eager_ms / 1e3), 1),
+                     "gflops_standard": round(flops / eager_ms / 1e6, 1), "status_ok": ok}
+        print(f"bench: batched {name} {count} problems: {eager_ms:.2f} ms eager, {graph_ms:.2f} ms graph",
+              file=sys.stderr, flush=True)
+        del bt, pristine, g
+        torch.cuda.empty_cache()
     return out
 
 

@@ -231,37 +231,40 @@ tqr_status tqr_solve_ls_mixed(int64_t m, int64_t n, int64_t nrhs, const double *
 
 /* ---- Batched factorisation: many independent problems in one launch ----
  * Each problem is factorised exactly as tqr_factor does it (the tiled
- * algorithm of Sec. 3.1, Algorithm 1, inner block 16), with its own tile
- * size.  One persistent launch; a workgroup takes the next problem from a
- * counter, converts it to tiles, runs its tasks in the order of Algorithm 1
- * and converts it back, so problems are independent of the schedule and of
- * each other (bitwise).  Problems are taken in array order: put the largest
+ * algorithm of Sec. 3.1, Algorithm 1) with its own tile size and inner block.
+ * One persistent launch; a workgroup takes the next problem from a counter,
+ * converts it to tiles, runs its tasks in the order of Algorithm 1 and
+ * converts it back, so problems are independent of the schedule and of each
+ * other (bitwise).  Problems are taken in array order: put the largest
  * first. */
 typedef struct tqr_batch_problem {
     int64_t m, n, lda;   /* m >= n >= 0, lda >= max(1, m) */
     double *A;           /* device, column-major; overwritten as by tqr_factor */
-    double *T;           /* device, tqr_t_elems(m, n, tile_b, 16) doubles, written */
-    int32_t tile_b;      /* 16, 32, 64 or 128 */
-    int32_t reserved;    /* 0 */
+    double *T;           /* device, tqr_t_elems(m, n, tile_b, inner_ib) doubles, written */
+    int32_t tile_b;      /* with inner_ib one of 16/16, 32/16, 32/32, 64/16, 64/32, 64/64, 128/16, 128/32 */
+    int32_t inner_ib;    /* 16, 32 or 64; 0 means 16 */
     int64_t work_offset; /* byte offset of the problem's tiles in work: set by tqr_batch_plan */
 } tqr_batch_problem;
 
 /* Host-side plan: checks every problem and sets its work_offset.  Returns
  * the workspace bytes that tqr_factor_batched needs, or -1 (count < 0),
  * -2 (problems null, or a problem with m < n, n < 0, lda < max(1, m), a
- * null A or T with m*n > 0, or an unsupported tile_b: the message names the
- * index). */
+ * null A or T with m*n > 0, or an unsupported (tile_b, inner_ib): the
+ * message names the index). */
 int64_t tqr_batch_plan(int64_t count, tqr_batch_problem *problems);
 
 /* Factorises the planned problems.  d_problems: device copy of the planned
- * array (count entries); work: tqr_batch_plan's bytes; d_status (optional
- * device int): 0, or i+1 when problem i had an unsupported tile_b (it is
- * skipped).  workgroups: 0 for one per resident slot, else at most that
- * many.  Enqueued on stream; no host synchronisation, no memset (the launch
- * may be captured in a graph).  Errors: -1 count, -2 d_problems null,
- * -3 work null, -4 work_bytes below 256, -7 workgroups < 0. */
+ * array (count entries); work: tqr_batch_plan's bytes; precision:
+ * TQR_PRECISION_FP64, or TQR_PRECISION_FP32_UPDATES (every problem's LARFB
+ * and SSRFB on the FP32 matrix cores, as tqr_factor_ex does it; inner_ib 16
+ * only); d_status (optional device int): 0, or i+1 when problem i's
+ * (tile_b, inner_ib) is not supported for the precision (it is skipped).
+ * workgroups: 0 for one per resident slot, else at most that many.
+ * Enqueued on stream; no host synchronisation, no memset (the launch may be
+ * captured in a graph).  Errors: -1 count, -2 d_problems null, -3 work null,
+ * -4 work_bytes below 256, -6 workgroups < 0, -7 precision. */
 tqr_status tqr_factor_batched(int64_t count, const tqr_batch_problem *d_problems, void *work, int64_t work_bytes,
-                              int32_t *d_status, int32_t workgroups, hipStream_t stream);
+                              int32_t *d_status, int32_t workgroups, int32_t precision, hipStream_t stream);
 
 /* ---- Factorisation without a workspace argument ----
  * For callers that cannot allocate device memory: code under HIP graph

@@ -57,7 +57,7 @@ class BatchProblem(ctypes.Structure):
         ("A", ctypes.c_void_p),
         ("T", ctypes.c_void_p),
         ("tile_b", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("inner_ib", ctypes.c_int32),
         ("work_offset", ctypes.c_int64),
     ]
 
@@ -98,7 +98,7 @@ def lib() -> ctypes.CDLL:
         L.tqr_solve_ls_mixed.restype = i32
         L.tqr_batch_plan.argtypes = [i64, ctypes.POINTER(BatchProblem)]
         L.tqr_batch_plan.restype = i64
-        L.tqr_factor_batched.argtypes = [i64, vp, vp, i64, vp, ctypes.c_int32, vp]
+        L.tqr_factor_batched.argtypes = [i64, vp, vp, i64, vp, ctypes.c_int32, ctypes.c_int32, vp]
         L.tqr_factor_batched.restype = i32
         L.tqr_last_error_string.argtypes = []
         L.tqr_last_error_string.restype = ctypes.c_char_p
@@ -320,23 +320,27 @@ class Batch:
     """Many independent problems factorised in one launch (tqr_factor_batched).
 
     ``shapes`` is a list of (m, n) with m >= n; ``tile_bs`` the tile size of
-    each problem (16, 32 or 64; see autotune.tile_for).  The matrices live
+    each problem and ``inner_ibs`` its inner block (default 16; see
+    autotune.tiling_for); ``precision`` PRECISION_FP64 or
+    PRECISION_FP32_UPDATES for the whole batch.  The matrices live
     column-major, back to back, in one device buffer ``A``; ``matrix(i)`` is
     problem i's view.  Problems are launched largest first (by the standard
     flop count), which the result does not depend on."""
 
-    def __init__(self, shapes, tile_bs, device="cuda"):
+    def __init__(self, shapes, tile_bs, inner_ibs=None, device="cuda", precision: int = PRECISION_FP64):
         self.shapes = [(int(m), int(n)) for m, n in shapes]
         self.tile_bs = [int(b) for b in tile_bs]
-        if len(self.tile_bs) != len(self.shapes):
-            raise ValueError("one tile size per problem")
+        self.inner_ibs = [16] * len(self.shapes) if inner_ibs is None else [int(ib) for ib in inner_ibs]
+        self.precision = int(precision)
+        if len(self.tile_bs) != len(self.shapes) or len(self.inner_ibs) != len(self.shapes):
+            raise ValueError("one tile size and inner block per problem")
         count = len(self.shapes)
         a_off, t_off, a, t = [], [], 0, 0
-        for (m, n), b in zip(self.shapes, self.tile_bs):
+        for (m, n), b, ib in zip(self.shapes, self.tile_bs, self.inner_ibs):
             a_off.append(a)
             t_off.append(t)
             a += m * n
-            t += max(t_elems(m, n, b, 16), 0)
+            t += max(t_elems(m, n, b, ib), 0)
         self.A = torch.zeros(max(a, 1), dtype=torch.float64, device=device)
         self.T = torch.zeros(max(t, 1), dtype=torch.float64, device=device)
         self.a_off, self.t_off = a_off, t_off
@@ -345,7 +349,8 @@ class Batch:
         base_a, base_t = self.A.data_ptr(), self.T.data_ptr()
         for slot, i in enumerate(order):
             m, n = self.shapes[i]
-            probs[slot] = BatchProblem(m, n, max(1, m), base_a + 8 * a_off[i], base_t + 8 * t_off[i], self.tile_bs[i], 0, 0)
+            probs[slot] = BatchProblem(m, n, max(1, m), base_a + 8 * a_off[i], base_t + 8 * t_off[i], self.tile_bs[i],
+                                       self.inner_ibs[i], 0)
         nb = int(lib().tqr_batch_plan(count, probs))
         if nb < 0:
             _check("tqr_batch_plan", nb)
@@ -370,12 +375,13 @@ class Batch:
 
     def t_slots(self, i: int) -> torch.Tensor:
         m, n = self.shapes[i]
-        return self.T[self.t_off[i]:self.t_off[i] + t_elems(m, n, self.tile_bs[i], 16)]
+        return self.T[self.t_off[i]:self.t_off[i] + t_elems(m, n, self.tile_bs[i], self.inner_ibs[i])]
 
     def factor(self, workgroups: int = 0) -> None:
         rc = lib().tqr_factor_batched(self.count, ctypes.c_void_p(self.desc.data_ptr() if self.count else 0),
                                       ctypes.c_void_p(self.work.data_ptr()), self.work.numel(),
-                                      ctypes.c_void_p(self.status.data_ptr()), int(workgroups), _stream())
+                                      ctypes.c_void_p(self.status.data_ptr()), int(workgroups), self.precision,
+                                      _stream())
         _check("tqr_factor_batched", rc)
 
 
