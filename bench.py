@@ -182,26 +182,28 @@ def cpu_baseline(A_host, seconds):
 def serving_leg(count: int, pool_size: int = 96):
     """The serving loop on the least-squares request stream (m log-uniform in
     [256, 8192], n uniform in [m/8, m], 1-4 right-hand sides, cond
-    log-uniform in [1e1, 1e6], Poisson arrivals): `count` requests at the
-    target rate 2000 req/s, which saturates one GPU (throughput and queueing
-    latency), and a third as many at 100 req/s (below saturation).  The
-    requests' matrices come from a pool of `pool_size` generated requests
-    (arrival i carries pool entry i mod pool_size), so that a thousand
-    requests need neither a thousand host generations nor their pinned
-    memory.  Host data pinned before the clock starts; copies in and out
-    timed."""
+    log-uniform in [1e1, 1e6], Poisson arrivals), answered by the mixed
+    solver (FP32-update factor + FP64 CGLS): `count` requests at the target
+    rate 2000 req/s, which saturates one GPU (throughput and queueing
+    latency), and a third as many at 100 req/s (below saturation); the FP64
+    solver on the 2000 req/s stream beside it.  The requests' matrices come
+    from a pool of `pool_size` generated requests (arrival i carries pool
+    entry i mod pool_size), so that a thousand requests need neither a
+    thousand host generations nor their pinned memory.  Host data pinned
+    before the clock starts; copies in and out timed."""
     from paper_0707_3548_amd import serving, workloads
 
     out = {"workload": f"least-squares requests, m log-uniform [256, 8192], n uniform [m/8, m], 1-4 RHS, "
                        f"cond log-uniform [1e1, 1e6], Poisson arrivals, matrices from a pool of {pool_size}; "
-                       "FP64 solve (factor, Q^T B, back substitution) per request, 8 streams, admission by "
-                       "HBM footprint"}
+                       "FP64 answers from the mixed solver (FP32-update factor + FP64 CGLS, accepted at a "
+                       "backward-error estimate <= 1e-14) or the FP64 solver, 8 streams, admission by HBM footprint"}
     pool_spec = workloads.arrivals(rate=1.0, count=pool_size, seed=5)
     pool = [workloads.ls_request(r["m"], r["n"], r["nrhs"], r["cond"], r["seed"])[:2] for r in pool_spec]
-    for name, rate, cnt, seed in (("offered_2000_per_s", 2000.0, count, 3),
-                                  ("offered_100_per_s", 100.0, max(1, count // 3), 4)):
+    for name, solver, rate, cnt, seed in (("mixed_offered_2000_per_s", "mixed", 2000.0, count, 3),
+                                          ("mixed_offered_100_per_s", "mixed", 100.0, max(1, count // 3), 4),
+                                          ("fp64_offered_2000_per_s", "fp64", 2000.0, count, 3)):
         arr = workloads.arrivals(rate=rate, count=cnt, seed=seed)
-        ex = serving.GpuExecutor(slots=8)
+        ex = serving.GpuExecutor(slots=8, solver=solver)
         prepared = {}
         reqs = []
         for i, r in enumerate(arr):
@@ -218,12 +220,16 @@ def serving_leg(count: int, pool_size: int = 96):
         span = max(c.t_done for c in done) - min(c.t_arrive for c in done)
         st["gflop_per_s"] = sum(2.0 * r.n * r.n * (r.m - r.n / 3.0) for r in reqs) / span / 1e9
         bad = sum(not c.result["ok"] for c in done)
-        out[name] = {k: round(v, 3) for k, v in st.items()} | {"offered_per_s": rate,
-                                                             "peak_in_flight": sch.peak_inflight,
-                                                             "peak_hbm_gb": round(sch.peak_bytes / 1e9, 3),
-                                                             "failed": bad}
-        print(f"bench: serving {cnt} requests at {rate:g} req/s: p50 {st['p50_ms']:.1f} ms, "
-              f"p99 {st['p99_ms']:.1f} ms, {st['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
+        row = {k: round(v, 3) for k, v in st.items()} | {"offered_per_s": rate, "peak_in_flight": sch.peak_inflight,
+                                                        "peak_hbm_gb": round(sch.peak_bytes / 1e9, 3), "failed": bad}
+        if solver == "mixed":
+            its = [r["iterations"] for c in done for r in (c.result["refine"] or [])]
+            row["cgls_iterations_mean"] = round(float(sum(its)) / max(1, len(its)), 2)
+            row["cgls_iterations_max"] = max(its) if its else 0
+        out[name] = row
+        print(f"bench: serving {solver} {cnt} requests at {rate:g} req/s: p50 {st['p50_ms']:.1f} ms, "
+              f"p99 {st['p99_ms']:.1f} ms, {st['solves_per_s']:.1f} solves/s, {bad} failed", file=sys.stderr,
+              flush=True)
     return out
 
 

@@ -93,16 +93,22 @@ def test_size_rules():
 
 
 @pytest.mark.gpu
-def test_answers_are_the_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("solver", ["mixed", "fp64"])
+def test_answers_are_the_same_alone_and_in_the_mix(solver):
+    """Every answer is bitwise the same alone and in the mix (the factor does
+    not depend on the schedule or the worker count, and the refinement's
+    sums run in a fixed order), is accepted (info, status and, for the mixed
+    solver, the refinement's convergence), and meets the FP64 backward-error
+    bound against the oracle."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import oracle
     from paper_0707_3548_amd import workloads
-    print("case serving mix of 16 requests", flush=True)
+    print(f"case serving mix of 16 requests, solver {solver}", flush=True)
     arr = workloads.arrivals(rate=2000.0, count=16, seed=21, m_lo=48, m_hi=700, cond_lo=1e1, cond_hi=1e6)
     data = [workloads.ls_request(r["m"], r["n"], r["nrhs"], r["cond"], r["seed"]) for r in arr]
-    ex = serving.GpuExecutor(slots=4)
+    ex = serving.GpuExecutor(slots=4, solver=solver)
 
     def requests():
         return [ex.prepare(serving.Request(i, r["t"], r["m"], r["n"], r["nrhs"]), A, b)
@@ -119,7 +125,25 @@ def test_answers_are_the_same_alone_and_in_the_mix():
     for i, (A, b, _) in enumerate(data):
         Xm = mix[i].result["X"].numpy().T
         Xa = alone[i].result["X"].numpy().T
-        assert mix[i].result["ok"]
+        assert mix[i].result["ok"], mix[i].result
         assert np.array_equal(Xm, Xa), f"request {i} differs between the mix and alone"
         for c in range(b.shape[1]):
             assert oracle.ls_backward_error(A, Xm[:, c], b[:, c]) < 1e-14
+
+
+@pytest.mark.gpu
+def test_a_request_that_does_not_converge_counts_as_failed():
+    """A mixed solve whose refinement is cut off (one iteration on a cond 1e5
+    problem) is reported as not ok, not as an answer."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0707_3548_amd import workloads
+    print("case serving refinement cut off", flush=True)
+    A, b, _ = workloads.ls_request(600, 300, 1, 1e5, seed=22)
+    ex = serving.GpuExecutor(slots=1, solver="mixed", iterations=1)
+    req = ex.prepare(serving.Request(0, 0.0, 600, 300, 1), A, b)
+    done = serving.Scheduler(1, 1 << 34, ex.launch, ex.poll).run([req])
+    res = done[0].result
+    assert not res["ok"]
+    assert res["refine"][0]["stop"] == 3   # the iteration limit
