@@ -236,8 +236,9 @@ def serving_leg(count: int, pool_size: int = 96):
 def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
     """The FP32 precision tier: (1) the same 8192x8192 factorisation with the
     trailing updates on the FP32 matrix cores (FP64 panels), timed like the
-    headline; (2) least squares 16384x4096 at cond 1e2, 1e5 and 1e8, solved
-    in FP64 and mixed (FP32-update factor, or the FP64 factor, + FP64 CGLS),
+    headline, and with BF16 operands; (2) least squares 16384x4096 at cond
+    1e2, 1e5 and 1e8, solved in FP64 and mixed (FP32-, BF16- or FP64-update
+    factor + FP64 CGLS),
     inputs in HBM: times, iterations, the device's backward-error estimate,
     and the relative difference from the FP64 solution."""
     import numpy as np
@@ -249,22 +250,25 @@ def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
     src = tqr.fortran(torch.from_numpy(A_host).cuda())
     ws = tqr.Workspace(m, n, 0, b, ib)
     copies = [src.clone() for _ in range(2)]
-    ts = []
-    for s in range(steps + 2):
-        dA = copies[s % 2]
-        dA.copy_(src)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        tqr.factor(dA, b, ib, ws, precision=tqr.PRECISION_FP32_UPDATES, policy=tqr.POLICY_COLUMN)
-        e1.record()
-        torch.cuda.synchronize()
-        if s >= 2:
-            ts.append(e0.elapsed_time(e1))
-    ms = sorted(ts)[len(ts) // 2]
     fl = 2.0 * n * n * (m - n / 3.0)
-    out["fp32_updates_factor"] = {"workload": f"{m}x{n} N(0,1), tile_b={b}, inner_ib={ib}, LARFB/SSRFB on FP32 MFMA, "
-                                              "GEQRT/TSQRT in FP64", "ms_per_step": round(ms, 3),
-                                  "gflops_standard": round(fl / ms / 1e6, 1), "speedup_vs_fp64": round(fp64_ms / ms, 3)}
+    for name, prec, what in (("fp32_updates_factor", tqr.PRECISION_FP32_UPDATES, "on FP32 MFMA"),
+                             ("bf16_updates_factor", tqr.PRECISION_BF16_UPDATES, "on BF16 MFMA with FP32 accumulation")):
+        ts = []
+        for s in range(steps + 2):
+            dA = copies[s % 2]
+            dA.copy_(src)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            tqr.factor(dA, b, ib, ws, precision=prec, policy=tqr.POLICY_COLUMN)
+            e1.record()
+            torch.cuda.synchronize()
+            if s >= 2:
+                ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[len(ts) // 2]
+        out[name] = {"workload": f"{m}x{n} N(0,1), tile_b={b}, inner_ib={ib}, LARFB/SSRFB {what}, "
+                                 "GEQRT/TSQRT in FP64", "ms_per_step": round(ms, 3),
+                     "gflops_standard": round(fl / ms / 1e6, 1), "speedup_vs_fp64": round(fp64_ms / ms, 3)}
+    ms = out["fp32_updates_factor"]["ms_per_step"]
     del copies, ws, src
     torch.cuda.empty_cache()
 
@@ -288,8 +292,8 @@ def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
         return sorted(t[1:])[len(t[1:]) // 2]
 
     ls = {"workload": f"{lm}x{ln} least squares, A = U diag(s) V^T (U, V from QR of Gaussians, s log-spaced), "
-                      "one right-hand side b = A x + 1e-6 N(0,1); FP64 solve vs FP32-update factor + FP64 CGLS "
-                      "(at most 20 iterations, device stopping test)"}
+                      "one right-hand side b = A x + 1e-6 N(0,1); FP64 solve vs FP32-, BF16- or FP64-update factor "
+                      "+ FP64 CGLS (at most 20 iterations, device stopping test)"}
     for cond in (1e2, 1e5, 1e8):
         Ah, Bh, _ = workloads.ls_problem(lm, ln, cond, seed=41, nrhs=1)
         dA0 = tqr.fortran(torch.from_numpy(Ah).cuda())
@@ -312,7 +316,8 @@ def mixed_legs(A_host, b: int, ib: int, fp64_ms: float, steps: int = 5):
         t64 = time_it(run64)
         x64 = run64.X[:ln].cpu().numpy()
         row = {"fp64_ms": round(t64, 3)}
-        for name, prec in (("fp32_factor", tqr.PRECISION_FP32_UPDATES), ("fp64_factor", tqr.PRECISION_FP64)):
+        for name, prec in (("fp32_factor", tqr.PRECISION_FP32_UPDATES), ("bf16_factor", tqr.PRECISION_BF16_UPDATES),
+                           ("fp64_factor", tqr.PRECISION_FP64)):
             tmx = time_it(lambda e0, e1: runmx(e0, e1, prec))
             st = tqr.refine_stats(runmx.stats)[0]
             xmx = runmx.X.cpu().numpy()

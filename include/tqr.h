@@ -104,7 +104,8 @@ typedef struct tqr_options {
     int64_t timeout_ticks;     /* per-wait bound in device clock ticks; 0 = 2 s */
     void *event_begin;         /* hipEvent_t recorded on `stream` right before the  */
     void *event_end;           /* scheduler launch and right after it, or NULL     */
-    int32_t precision;         /* TQR_PRECISION_FP64 (0, default) or TQR_PRECISION_FP32_UPDATES */
+    int32_t precision;         /* TQR_PRECISION_FP64 (0, default), TQR_PRECISION_FP32_UPDATES or
+                                  TQR_PRECISION_BF16_UPDATES */
     int32_t reserved;          /* 0 */
 } tqr_options;
 
@@ -121,6 +122,11 @@ typedef struct tqr_options {
                                         reflectors, T) in FP64; inner_ib must be 16.  The
                                         factor is then accurate to FP32 rounding: a starting
                                         point for FP64 refinement (tqr_solve_ls_mixed). */
+#define TQR_PRECISION_BF16_UPDATES 2 /* as TQR_PRECISION_FP32_UPDATES, with the two large products of
+                                        LARFB/SSRFB taking BF16 operands (V, the strip, and W after
+                                        op(T)) and accumulating in FP32 on the BF16 matrix cores;
+                                        inner_ib 16 and tile_b 64, 128 or 256.  The factor is
+                                        accurate to BF16 rounding (about 4e-3 relative). */
 
 /* tqr_factor with explicit execution options (argument errors as
  * tqr_factor; -11 for a bad options struct). */
@@ -187,7 +193,8 @@ tqr_status tqr_solve_ls_ex(int64_t m, int64_t n, int64_t nrhs, double *A, int64_
  * min ||A X - B||_F for m >= n (the least-squares problem that QR solves,
  * Sec. 2.1).  A copy of A is factorised with the trailing updates on the
  * FP32 matrix cores (TQR_PRECISION_FP32_UPDATES; options may ask for
- * TQR_PRECISION_FP64 instead); the norms, reflectors and T stay FP64.  Then,
+ * TQR_PRECISION_BF16_UPDATES or TQR_PRECISION_FP64 instead); the norms,
+ * reflectors and T stay FP64.  Then,
  * for each right-hand side, CGLS in FP64 on min ||(A R^{-1}) y - b||,
  * x = R^{-1} y, from x = 0, with R the factor's triangle as a right
  * preconditioner: every product with A and A^T uses the caller's FP64 A, and

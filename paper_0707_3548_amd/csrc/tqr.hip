@@ -405,6 +405,8 @@ tqr_status tqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, int tile_
     if (check_opts(options) != TQR_OK) return set_err(-11, "bad tqr_options");
     if (options && options->precision == TQR_PRECISION_FP32_UPDATES && inner_ib != 16)
         return set_err(-11, "TQR_PRECISION_FP32_UPDATES needs inner_ib 16");
+    if (options && options->precision == TQR_PRECISION_BF16_UPDATES && (inner_ib != 16 || tile_b < 64))
+        return set_err(-11, "TQR_PRECISION_BF16_UPDATES needs inner_ib 16 and tile_b 64, 128 or 256");
     return dispatch(tile_b, inner_ib,
                     [&](const PairFns &f) { return f.factor(m, n, A, lda, T, work, stream, options, true); });
 }

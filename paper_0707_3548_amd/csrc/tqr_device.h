@@ -338,7 +338,30 @@ __device__ __forceinline__ void strip_store_f(const StripF<B> &s, double *col0, 
 // (floats); Tl: T(r, c) = Tl[16 c + r] (floats).  The TS form's top rows stay
 // FP64 in memory: W takes their float value and they are updated in FP64 by
 // the float correction.
-template <int B, bool TRANS, bool TS>
+// BF16 operands for v_mfma_f32_16x16x16bf16_1k, which takes in lane l the
+// four K values 4(l/16) .. 4(l/16)+3 of row l%16 of A and of column l%16 of
+// B and accumulates in FP32 with the output layout of the FP32 instruction.
+// The conversion rounds to nearest even (the gfx950 packed conversion, two
+// floats per instruction).
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bh2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ bf4 bf16x4(float a, float b, float c, float d) {
+    const bh2 lo = __builtin_convertvector(fl2{a, b}, bh2), hi = __builtin_convertvector(fl2{c, d}, bh2);
+    const uint32_t ulo = __builtin_bit_cast(uint32_t, lo), uhi = __builtin_bit_cast(uint32_t, hi);
+    return __builtin_bit_cast(bf4, (uint64_t)ulo | ((uint64_t)uhi << 32));
+}
+__device__ __forceinline__ f4 mfma_bf16(bf4 a, bf4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// BF16 variant (BF16 = true): the two large products take their operands in
+// BF16 (V, C, and W after op(T)) with FP32 accumulation, one instruction per
+// 16-row block where the FP32 form issues four: the four K-slices of the FP32
+// form are the four K values each lane group supplies, so the operands are
+// the same registers and LDS words, converted.  op(T) W stays FP32.
+template <int B, bool TRANS, bool TS, bool BF16 = false>
 __device__ __forceinline__ void panel_update_f32(StripF<B> &C, double *top, const float *Vl, int ldv, const float *Tl,
                                                  int c0, bool write_top = true) {
     const int l = lane_id();
@@ -351,10 +374,14 @@ __device__ __forceinline__ void panel_update_f32(StripF<B> &C, double *top, cons
     for (int rb = 0; rb < B / 16; ++rb) {
         if (!TS && rb < rb0) continue;
         const float *q = vp + 16 * rb;
-        W = mfma32(q[0], C.v[rb].x, W);
-        W = mfma32(q[4], C.v[rb].y, W);
-        W = mfma32(q[8], C.v[rb].z, W);
-        W = mfma32(q[12], C.v[rb].w, W);
+        if constexpr (BF16) {
+            W = mfma_bf16(bf16x4(q[0], q[4], q[8], q[12]), bf16x4(C.v[rb].x, C.v[rb].y, C.v[rb].z, C.v[rb].w), W);
+        } else {
+            W = mfma32(q[0], C.v[rb].x, W);
+            W = mfma32(q[4], C.v[rb].y, W);
+            W = mfma32(q[8], C.v[rb].z, W);
+            W = mfma32(q[12], C.v[rb].w, W);
+        }
     }
     double *tp = nullptr;
     d4 t = {0.0, 0.0, 0.0, 0.0};
@@ -381,14 +408,20 @@ __device__ __forceinline__ void panel_update_f32(StripF<B> &C, double *top, cons
     // perm(4a + b) = 4b + a
     const int pr = 4 * (l & 3) + ((l & 15) >> 2);
     const float *vq = Vl + 4 * (l >> 4) * ldv + pr;
+    bf4 w2b = {};
+    if constexpr (BF16) w2b = bf16x4(W2.x, W2.y, W2.z, W2.w);
 #pragma unroll
     for (int rb = 0; rb < B / 16; ++rb) {
         if (!TS && rb < rb0) continue;
         const float *q = vq + 16 * rb;
-        C.v[rb] = mfma32(q[0], W2.x, C.v[rb]);
-        C.v[rb] = mfma32(q[ldv], W2.y, C.v[rb]);
-        C.v[rb] = mfma32(q[2 * ldv], W2.z, C.v[rb]);
-        C.v[rb] = mfma32(q[3 * ldv], W2.w, C.v[rb]);
+        if constexpr (BF16) {
+            C.v[rb] = mfma_bf16(bf16x4(q[0], q[ldv], q[2 * ldv], q[3 * ldv]), w2b, C.v[rb]);
+        } else {
+            C.v[rb] = mfma32(q[0], W2.x, C.v[rb]);
+            C.v[rb] = mfma32(q[ldv], W2.y, C.v[rb]);
+            C.v[rb] = mfma32(q[2 * ldv], W2.z, C.v[rb]);
+            C.v[rb] = mfma32(q[3 * ldv], W2.w, C.v[rb]);
+        }
     }
 }
 

@@ -1138,7 +1138,7 @@ struct TileKernels {
         }
     }
 
-    template <bool TRANS, bool TS>
+    template <bool TRANS, bool TS, bool BF16 = false>
     __device__ __forceinline__ static void apply_dbuf_f32(StripF<B> &C, double *Top, const double *V, const double *T,
                                                           int col0, bool owner, double *smem, const Pipe &pp = Pipe{}) {
         static_assert(IB == 16, "the FP32 tier works with inner block 16");
@@ -1159,15 +1159,15 @@ struct TileKernels {
             const int c0 = (TRANS ? si : NB - 1 - si) * IB;
             float *cur = buf(si & 1);
             if (si + 1 < NB) stage_fetch(V, T, (TRANS ? si + 1 : NB - 2 - si) * IB, R);
-            panel_update_f32<B, TRANS, TS>(C, TS ? Top + (size_t)col0 * B : nullptr, cur, LDV, cur + (size_t)LDV * IB,
-                                           c0, owner);
+            panel_update_f32<B, TRANS, TS, BF16>(C, TS ? Top + (size_t)col0 * B : nullptr, cur, LDV,
+                                                 cur + (size_t)LDV * IB, c0, owner);
             if (si + 1 < NB) stage_commit_f(R, buf((si + 1) & 1));
             if (TRANS && pp.prev && t0 && si + 2 < NB) pipe_wait(pp, si + 3);
             __syncthreads();
         }
     }
 
-    template <bool TRANS>
+    template <bool TRANS, bool BF16 = false>
     __device__ __forceinline__ static void larfb_f32(const double *Vd, const double *Tkk, double *Cb, int cbeg, int cend,
                                                      double *smem) {
         const int want = cbeg + 16 * wave_id();
@@ -1175,11 +1175,11 @@ struct TileKernels {
         const bool owner = want < cend;
         StripF<B> C;
         strip_load_f<B>(C, Cb + (size_t)col0 * B, B);
-        apply_dbuf_f32<TRANS, false>(C, nullptr, Vd, Tkk, col0, owner, smem);
+        apply_dbuf_f32<TRANS, false, BF16>(C, nullptr, Vd, Tkk, col0, owner, smem);
         if (owner) strip_store_f<B>(C, Cb + (size_t)col0 * B, B);
     }
 
-    template <bool TRANS>
+    template <bool TRANS, bool BF16 = false>
     __device__ __forceinline__ static void ssrfb_f32(double *Top, double *Cb, const double *Vik, const double *Tik, int cbeg,
                                                      int cend, double *smem, const Pipe &pp = Pipe{}) {
         const int want = cbeg + 16 * wave_id();
@@ -1187,7 +1187,7 @@ struct TileKernels {
         const bool owner = want < cend;
         StripF<B> C;
         strip_load_f<B>(C, Cb + (size_t)col0 * B, B);
-        apply_dbuf_f32<TRANS, true>(C, Top, Vik, Tik, col0, owner, smem, pp);
+        apply_dbuf_f32<TRANS, true, BF16>(C, Top, Vik, Tik, col0, owner, smem, pp);
         if (owner) strip_store_f<B>(C, Cb + (size_t)col0 * B, B);
     }
 };
@@ -1195,7 +1195,9 @@ struct TileKernels {
 // ---------------------------------------------------------------------------
 // Task bodies
 // ---------------------------------------------------------------------------
-template <int B, int IB, bool F32 = false>
+// F32: LARFB/SSRFB on the FP32 matrix cores; with BF as well, their two
+// large products take BF16 operands (FP32 accumulation).
+template <int B, int IB, bool F32 = false, bool BF = false>
 struct FactorBody {
     using K = TileKernels<B, IB>;
     double *W;   // tiles
@@ -1249,14 +1251,14 @@ struct FactorBody {
             break;
         case LARFB:
             if constexpr (F32)
-                K::template larfb_f32<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem);
+                K::template larfb_f32<true, BF>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem);
             else
                 K::template larfb<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem);
             break;
         default:
             if constexpr (F32)
-                K::template ssrfb_f32<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend,
-                                            smem, pipe(t));
+                K::template ssrfb_f32<true, BF>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg,
+                                                cend, smem, pipe(t));
             else
                 K::template ssrfb<true>(tile(t.k, t.j), tile(t.i, t.j), tile(t.i, t.k), tslot(t.i, t.k), cbeg, cend, smem,
                                         pipe(t));
@@ -1371,8 +1373,8 @@ struct TrsmBody {
 // graph's order; returns how many.
 template <class G, class Body>
 __device__ __forceinline__ int early_successors(const G &, const Body &, const Task &) { return 0; }
-template <int B, int IB, bool F32>
-__device__ __forceinline__ int early_successors(const FactorGraph &g, const FactorBody<B, IB, F32> &b, const Task &t) {
+template <int B, int IB, bool F32, bool BF>
+__device__ __forceinline__ int early_successors(const FactorGraph &g, const FactorBody<B, IB, F32, BF> &b, const Task &t) {
     if (!b.prog || (t.kind != GEQRT && t.kind != TSQRT)) return 0;
     const int chain = t.i + 1 < g.p ? 1 : 0;
     if (t.kind == GEQRT) return chain;
@@ -1760,10 +1762,10 @@ tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, 
 
 // The factorisation body; with inner block 16 in persistent mode the R_kk
 // chain is pipelined (progress words cleared here, on the stream).
-template <int B, int IB, bool F32 = false>
-FactorBody<B, IB, F32> factor_body(double *W, double *T, double *Vd, const Sizes &z, void *work, void *sched,
+template <int B, int IB, bool F32 = false, bool BF = false>
+FactorBody<B, IB, F32, BF> factor_body(double *W, double *T, double *Vd, const Sizes &z, void *work, void *sched,
                                    const tqr_options *opt, hipStream_t stream) {
-    FactorBody<B, IB, F32> body{W, T, Vd, (int)z.p};
+    FactorBody<B, IB, F32, BF> body{W, T, Vd, (int)z.p};
     const bool serial = opt && opt->mode == TQR_MODE_SERIAL;
     if (IB == 16 && !serial) {
         body.prog = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(work) + z.prog_offset());
@@ -1796,6 +1798,15 @@ tqr_status factor_impl(int64_t m, int64_t n, double *A, int64_t lda, double *T, 
             const FactorBody<B, IB, true> body = factor_body<B, IB, true>(W, T, Vd, z, work, sched, opt, stream);
             g.helpers = body.helpers;
             st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
+        } else if (opt && opt->precision == TQR_PRECISION_BF16_UPDATES) {
+            if constexpr (B >= 64) {
+                const FactorBody<B, IB, true, true> body =
+                    factor_body<B, IB, true, true>(W, T, Vd, z, work, sched, opt, stream);
+                g.helpers = body.helpers;
+                st = run_graph(g, body, sched, TileKernels<B, IB>::LDS_BYTES, opt, stream, opt ? opt->status : nullptr);
+            } else {
+                return set_err(-11, "TQR_PRECISION_BF16_UPDATES needs tile_b 64, 128 or 256");
+            }
         } else {
             const FactorBody<B, IB> body = factor_body<B, IB>(W, T, Vd, z, work, sched, opt, stream);
             g.helpers = body.helpers;
@@ -1938,7 +1949,9 @@ inline tqr_status check_opts(const tqr_options *o) {
     if (o->policy != TQR_POLICY_PAPER && o->policy != TQR_POLICY_LOOKAHEAD && o->policy != TQR_POLICY_COLUMN)
         return -11;
     if (o->workgroups < 0) return -11;
-    if (o->precision != TQR_PRECISION_FP64 && o->precision != TQR_PRECISION_FP32_UPDATES) return -11;
+    if (o->precision != TQR_PRECISION_FP64 && o->precision != TQR_PRECISION_FP32_UPDATES &&
+        o->precision != TQR_PRECISION_BF16_UPDATES)
+        return -11;
     if (o->reserved != 0) return -11;
     return TQR_OK;
 }
@@ -2038,6 +2051,10 @@ tqr_status mixed_impl(int64_t m, int64_t n, int64_t nrhs, const double *A, int64
     tqr_status s1;
     if (o.precision == TQR_PRECISION_FP32_UPDATES) {
         const FactorBody<B, 16, true> body = factor_body<B, 16, true>(W, T, Vd, z, work, sched, &o, stream);
+        g.helpers = body.helpers;
+        s1 = run_graph(g, body, sched, TileKernels<B, 16>::LDS_BYTES, &o, stream, o.status);
+    } else if (o.precision == TQR_PRECISION_BF16_UPDATES) {
+        const FactorBody<B, 16, true, true> body = factor_body<B, 16, true, true>(W, T, Vd, z, work, sched, &o, stream);
         g.helpers = body.helpers;
         s1 = run_graph(g, body, sched, TileKernels<B, 16>::LDS_BYTES, &o, stream, o.status);
     } else {

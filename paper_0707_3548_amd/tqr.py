@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libtqr.so")
 MODE_PERSISTENT, MODE_SERIAL = 0, 1
 POLICY_PAPER, POLICY_LOOKAHEAD, POLICY_COLUMN = 0, 1, 2
 TQR_EDEVICE, TQR_EABORTED, TQR_ESCRATCH = -1000, -1001, -1002
-PRECISION_FP64, PRECISION_FP32_UPDATES = 0, 1
+PRECISION_FP64, PRECISION_FP32_UPDATES, PRECISION_BF16_UPDATES = 0, 1, 2
 NOALLOC_SCRATCH_BYTES = 128 << 20  # TQR_NOALLOC_SCRATCH_BYTES
 
 

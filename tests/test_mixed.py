@@ -172,3 +172,67 @@ def test_mixed_ls_beyond_the_fp32_factor_reports_stagnation_honestly():
     assert eta < 1e-14 and st["stop"] == tqr.REFINE_CONVERGED
     Xo, _ = oracle.lstsq(A, Bh)
     assert np.linalg.norm(Xh - Xo) / np.linalg.norm(Xo) < cond * 1e-13
+
+
+U_BF16 = 2.0 ** -8   # unit roundoff of BF16 (8 significand bits)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m,n,b", [(512, 512, 64), (777, 500, 128), (1024, 1024, 256)])
+def test_bf16_updates_factor(m, n, b):
+    """BF16 tier: the trailing updates' products take BF16 operands, so R
+    carries BF16 rounding (R within 5 u_bf16 of the oracle, ||A - QR|| within
+    5 u_bf16 of ||A||), while Q, built from the FP64 panels, stays orthogonal
+    to FP64 accuracy; and the tier really ran (its R differs from the FP32
+    tier's by more than FP32 rounding)."""
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    print(f"case bf16-updates factor m={m} n={n} b={b}", flush=True)
+    A = workloads.gaussian(m, n, seed=35)
+    dA = tqr.fortran(torch.from_numpy(A).cuda())
+    ws = tqr.Workspace(m, n, 0, b, 16)
+    tqr.factor(dA, b, 16, ws, precision=tqr.PRECISION_BF16_UPDATES)
+    torch.cuda.synchronize()
+    R = np.triu(dA.cpu().numpy()[:n, :])
+    _, R_or = oracle.qr(A)
+    e_r = oracle.rel_fro(oracle.sign_normalize(R), R_or)
+    E = torch.zeros((n, m), dtype=torch.float64, device="cuda").t()
+    E[torch.arange(n), torch.arange(n)] = 1.0
+    tqr.apply_q(dA, ws.T, E, b, 16)
+    torch.cuda.synchronize()
+    Q = E.cpu().numpy()
+    e_f = oracle.fact_error(A, Q, R)
+    print(f"  R error {e_r:.3e}, factorisation error {e_f:.3e}", flush=True)
+    assert e_r < 5 * U_BF16 and e_f < 5 * U_BF16
+    assert oracle.orth_error(Q) <= 10 * n * oracle.EPS
+    dF = tqr.fortran(torch.from_numpy(A).cuda())
+    tqr.factor(dF, b, 16, precision=tqr.PRECISION_FP32_UPDATES)
+    torch.cuda.synchronize()
+    R32 = np.triu(dF.cpu().numpy()[:n, :])
+    assert oracle.rel_fro(R, R32) > 100 * U32
+
+
+@pytest.mark.gpu
+def test_mixed_ls_with_bf16_factor():
+    """BF16-update factor + FP64 CGLS: at cond 1e2 (cond * u_bf16 < 1) the
+    refinement reaches FP64 accuracy; at cond 1e4 the BF16 R is no usable
+    preconditioner and the solver reports stagnation with an estimate that
+    agrees with the oracle's backward error."""
+    torch = _torch()
+    from paper_0707_3548_amd import tqr, workloads
+    for cond, expect_converge in ((1e2, True), (1e4, False)):
+        print(f"case mixed LS bf16 factor cond={cond:g}", flush=True)
+        A, Bh, _ = workloads.ls_problem(800, 400, cond, seed=36, nrhs=1)
+        dA = tqr.fortran(torch.from_numpy(A).cuda())
+        dB = tqr.fortran(torch.from_numpy(Bh).cuda())
+        X, _, info, stats = tqr.solve_ls_mixed(dA, dB, 128, iterations=60, precision=tqr.PRECISION_BF16_UPDATES)
+        torch.cuda.synchronize()
+        st = tqr.refine_stats(stats)[0]
+        eta = oracle.ls_backward_error(A, X.cpu().numpy()[:, 0], Bh[:, 0])
+        print(f"  {st}, oracle eta {eta:.3e}", flush=True)
+        assert int(info.item()) == 0
+        if expect_converge:
+            assert st["stop"] == tqr.REFINE_CONVERGED and eta < 1e-14
+        elif eta >= 1e-14:
+            assert st["stop"] in (tqr.REFINE_STAGNATED, tqr.REFINE_MAX_ITERATIONS)
+            assert 0.1 < st["eta"] / eta < 10
