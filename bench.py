@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_factor_8192_b256.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0707_3548_amd", "csrc", f)
                   for f in ("tqr.hip", "tqr_inst.hip", "tqr_batched.hip", "tqr_impl.h", "tqr_device.h", "tqr_graph.h",
-                            "tqr_narrow.h")] + \
+                            "tqr_narrow.h", "tqr_offsets.h")] + \
     [os.path.join(ROOT, "paper_0707_3548_amd", "build.py")]
 
 

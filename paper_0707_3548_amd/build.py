@@ -28,7 +28,7 @@ PAIRS = [(16, 16), (32, 16), (32, 32), (64, 16), (64, 32), (64, 64), (128, 16), 
 UNITS = [("tqr", "tqr.hip", []), ("tqr_batched", "tqr_batched.hip", []), ("tqr_noalloc", "tqr_noalloc.hip", [])] + [
     (f"tqr_b{b}_ib{ib}", "tqr_inst.hip", [f"-DTQR_INST_B={b}", f"-DTQR_INST_IB={ib}"]) for b, ib in PAIRS]
 SOURCES = [os.path.join(CSRC, f) for f in ("tqr.hip", "tqr_batched.hip", "tqr_noalloc.hip", "tqr_inst.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("tqr_impl.h", "tqr_device.h", "tqr_graph.h", "tqr_narrow.h")] + \
+HEADERS = [os.path.join(CSRC, f) for f in ("tqr_impl.h", "tqr_device.h", "tqr_graph.h", "tqr_narrow.h", "tqr_offsets.h")] + \
     [os.path.join(ROOT, "include", "tqr.h")]
 
 # Scalar registers a persistent-scheduler kernel may spill (into vector

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tqr_offsets.h"
+
 namespace tqr {
 
 constexpr int NT = 256;           // threads of every workgroup (4 wave64)
@@ -111,9 +113,8 @@ struct Strip {
     d4 v[B / 16];
 };
 
-// A-operand row m (0..15) of a product accumulated into a strip's row block
-// reads source row strip_row_perm(m) = 4(m % 4) + m / 4 of that block.
-__device__ __forceinline__ int strip_row_perm(int m) { return 4 * (m & 3) + (m >> 2); }
+// (strip_row_perm and the operand offsets of the strip updates are in
+// tqr_offsets.h, shared with a host-side bounds check.)
 
 template <int B>
 __device__ __forceinline__ void strip_load(Strip<B> &s, const double *col0, int ld) {
@@ -181,16 +182,11 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
     // The operands of row block rb+1 are read from LDS before the products of
     // row block rb are issued (the scheduling fences keep that order): with
     // one wave per SIMD nothing else hides the LDS latency.
-    const double *vp = Vl + (l & 15) * ldv + 4 * (l >> 4);
     auto read_vt = [&](int rb, double (&o)[NA][4]) {
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            const double *q = vp + 16 * a * ldv + 16 * rb;
-            o[a][0] = q[0];
-            o[a][1] = q[1];
-            o[a][2] = q[2];
-            o[a][3] = q[3];
-        }
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[a][r] = Vl[upd_vt_off(l, ldv, a, rb, r)];
     };
     // op(T) operands of the W2 = op(T) W products, read ahead of them
     double tv[NA][NA][4];
@@ -199,11 +195,8 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
             if (TRANS ? (a > o) : (a < o)) continue;  // T is upper triangular
-            const double *tq = TRANS ? Tl + (16 * o + (l & 15)) * IB + 16 * a + (l >> 4)
-                                     : Tl + (16 * a + (l >> 4)) * IB + 16 * o + (l & 15);
-            const int st = TRANS ? 4 : 4 * IB;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) tv[o][a][r] = tq[r * st];
+            for (int r = 0; r < 4; ++r) tv[o][a][r] = Tl[upd_t_off(TRANS, l, IB, o, a, r)];
         }
     double va[NA][4], vn[NA][4];
     read_vt(rb0, va);
@@ -233,16 +226,11 @@ __device__ __forceinline__ void panel_update(Strip<B> &C, double *top, const dou
     }
     // A operand of the update C -= V W2, k-slice (a, r):
     // V[16rb + strip_row_perm(l%16)][16a + 4r + l/16]
-    const double *vq = Vl + (l >> 4) * ldv + strip_row_perm(l & 15);
     auto read_v = [&](int rb, double (&o)[NA][4]) {
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            const double *q = vq + 16 * a * ldv + 16 * rb;
-            o[a][0] = q[0];
-            o[a][1] = q[4 * ldv];
-            o[a][2] = q[8 * ldv];
-            o[a][3] = q[12 * ldv];
-        }
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[a][r] = Vl[upd_v_off(l, ldv, a, rb, r)];
     };
     read_v(rb0, va);
     if (TS) {
@@ -369,18 +357,19 @@ __device__ __forceinline__ void panel_update_f32(StripF<B> &C, double *top, cons
     // W = V^T C; k-slice (rb, r): rows 16rb + 4r + {0..3}; W row a in lane
     // group a/4, element a%4
     f4 W = {0.0f, 0.0f, 0.0f, 0.0f};
-    const float *vp = Vl + (l & 15) * ldv + (l >> 4);
 #pragma unroll
     for (int rb = 0; rb < B / 16; ++rb) {
         if (!TS && rb < rb0) continue;
-        const float *q = vp + 16 * rb;
+        float q[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) q[r] = Vl[updf_vt_off(l, ldv, rb, r)];
         if constexpr (BF16) {
-            W = mfma_bf16(bf16x4(q[0], q[4], q[8], q[12]), bf16x4(C.v[rb].x, C.v[rb].y, C.v[rb].z, C.v[rb].w), W);
+            W = mfma_bf16(bf16x4(q[0], q[1], q[2], q[3]), bf16x4(C.v[rb].x, C.v[rb].y, C.v[rb].z, C.v[rb].w), W);
         } else {
             W = mfma32(q[0], C.v[rb].x, W);
-            W = mfma32(q[4], C.v[rb].y, W);
-            W = mfma32(q[8], C.v[rb].z, W);
-            W = mfma32(q[12], C.v[rb].w, W);
+            W = mfma32(q[1], C.v[rb].y, W);
+            W = mfma32(q[2], C.v[rb].z, W);
+            W = mfma32(q[3], C.v[rb].w, W);
         }
     }
     double *tp = nullptr;
@@ -394,7 +383,7 @@ __device__ __forceinline__ void panel_update_f32(StripF<B> &C, double *top, cons
     f4 W2 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const float a = TRANS ? Tl[(l & 15) * 16 + 4 * (l >> 4) + r] : Tl[(4 * (l >> 4) + r) * 16 + (l & 15)];
+        const float a = Tl[updf_t_off(TRANS, l, r)];
         W2 = mfma32(a, W[r], W2);
     }
     if (TS && write_top) {
@@ -406,21 +395,21 @@ __device__ __forceinline__ void panel_update_f32(StripF<B> &C, double *top, cons
     W2 = -W2;
     // C -= V W2; output row d of an MFMA is strip row 16rb + perm(d),
     // perm(4a + b) = 4b + a
-    const int pr = 4 * (l & 3) + ((l & 15) >> 2);
-    const float *vq = Vl + 4 * (l >> 4) * ldv + pr;
     bf4 w2b = {};
     if constexpr (BF16) w2b = bf16x4(W2.x, W2.y, W2.z, W2.w);
 #pragma unroll
     for (int rb = 0; rb < B / 16; ++rb) {
         if (!TS && rb < rb0) continue;
-        const float *q = vq + 16 * rb;
+        float q[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) q[r] = Vl[updf_v_off(l, ldv, rb, r)];
         if constexpr (BF16) {
-            C.v[rb] = mfma_bf16(bf16x4(q[0], q[ldv], q[2 * ldv], q[3 * ldv]), w2b, C.v[rb]);
+            C.v[rb] = mfma_bf16(bf16x4(q[0], q[1], q[2], q[3]), w2b, C.v[rb]);
         } else {
             C.v[rb] = mfma32(q[0], W2.x, C.v[rb]);
-            C.v[rb] = mfma32(q[ldv], W2.y, C.v[rb]);
-            C.v[rb] = mfma32(q[2 * ldv], W2.z, C.v[rb]);
-            C.v[rb] = mfma32(q[3 * ldv], W2.w, C.v[rb]);
+            C.v[rb] = mfma32(q[1], W2.y, C.v[rb]);
+            C.v[rb] = mfma32(q[2], W2.z, C.v[rb]);
+            C.v[rb] = mfma32(q[3], W2.w, C.v[rb]);
         }
     }
 }
