@@ -404,6 +404,22 @@ def traffic_from_profile(per_launch_flops):
     return prof.get("hbm_bytes_per_launch")
 
 
+def counters_from_profile():
+    """The matrix-core counters of the committed rocprofv3 summary, if it was
+    taken on the current kernel sources."""
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            prof = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if prof.get("kernel_source_hash") != kernel_source_hash() or "mfma_busy_fraction" not in prof:
+        return None
+    return {"mfma_busy_fraction": round(prof["mfma_busy_fraction"], 4),
+            "mfma_f64_flops_per_launch": prof["mfma_f64_flops_per_launch"],
+            "source": "rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs); "
+                      "SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 (profiles/factor_8192_b256.md)"}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -499,6 +515,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved_tf / FP64_MFMA_PEAK_TFLOPS, 4),
                      "traffic": traffic},
+        "counters": counters_from_profile(),
         "cpu_baseline": cpu,
         "check": check,
         "tall_skinny": tall,
