@@ -502,7 +502,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"FP64 tiled QR of one {n}x{n} N(0,1) matrix, tile_b={b}, inner_ib={ib}, "
                                + ("the plain tqr_factor call (persistent task-graph scheduler, default priorities: "
-                                  "GEQRT > TSQRT > updates by their column's distance from the current panel)"
+                                  "GEQRT > TSQRT > updates by their column's distance from the current panel, "
+                                  "one worker in four serving the farthest columns first)"
                                   if args.policy == "default" else
                                   f"tqr_factor_ex with the {args.policy} priority policy"),
                    "m": n, "n": n, "tile_b": b, "inner_ib": ib},

@@ -169,14 +169,25 @@ __device__ void abort_run(const Sched &s, int nworkers) {
     broadcast_stop(s, nworkers);
 }
 
+// Far-first workers (RunOpts::far_every): under the column policy one worker
+// in far_every serves the update levels farthest column first, so that work
+// for the columns the panels reach later keeps moving even while nearer
+// levels never run dry, instead of piling up in the last level and holding
+// up a panel when its column comes near.  Measured on the square
+// factorisation (one worker in four); on tall grids, where the chains of
+// TSQRT tasks pace the run, they slow it down and are not used.
+constexpr int kFarEverySquare = 4;
+
 // One look at the ready queues: takes the head task of the highest-priority
-// non-empty level.  Returns the task id, -1 if every level looked empty or
-// other workers took what there was, -2 after an abort.
-__device__ int32_t try_pop(const Sched &s, uint64_t deadline, uint32_t &spins, int nworkers) {
+// non-empty level (for a far-first worker, levels 2.. in reverse).  Returns
+// the task id, -1 if every level looked empty or other workers took what
+// there was, -2 after an abort.
+__device__ int32_t try_pop(const Sched &s, bool far_first, uint64_t deadline, uint32_t &spins, int nworkers) {
     uint64_t w[kLevels];
 #pragma unroll
     for (int l = 0; l < kLevels; ++l) w[l] = flag_load(&s.st->ht[l]);
-    for (int l = 0; l < kLevels; ++l) {
+    for (int r = 0; r < kLevels; ++r) {
+        const int l = far_first && r >= 2 ? kLevels + 1 - r : r;
         uint64_t cur = w[l];
         // a failed exchange returns the current word: retry at once while
         // the level still holds work (a push also changes the word)
@@ -267,20 +278,21 @@ __device__ __forceinline__ void sched_store_load_fence() {
 }
 
 template <class G>
-__device__ int32_t idle_wait(const G &g, int policy, const Sched &s, uint32_t nsinks,
+__device__ int32_t idle_wait(const G &g, int policy, int far_every, const Sched &s, uint32_t nsinks,
                              const volatile int32_t *abort_flag, uint64_t deadline, int me, int nworkers) {
     uint32_t spins = 0;
     uint64_t *word = &s.st->idle[me >> 6];
     const uint64_t bit = 1ull << (me & 63);
     int32_t *mb = &s.mbox[me * kMboxStride];
+    const bool far_first = far_every > 0 && me % far_every == far_every - 1;
     for (;;) {
         if (flag_load(&s.st->status) != 0) return -1;
-        int32_t t = try_pop(s, deadline, spins, nworkers);
+        int32_t t = try_pop(s, far_first, deadline, spins, nworkers);
         if (t >= 0) return t;
         if (t == -2) return -1;
         __hip_atomic_fetch_or(word, bit, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
         sched_store_load_fence();
-        t = try_pop(s, deadline, spins, nworkers);
+        t = try_pop(s, far_first, deadline, spins, nworkers);
         if (t >= 0) {
             const int32_t m = withdraw_idle(s, word, bit, mb, deadline, spins, nworkers);
             if (m >= 0) {
@@ -434,6 +446,7 @@ struct RunOpts {
     const volatile int32_t *abort_flag;
     int64_t timeout;
     int policy;
+    int far_every;  // 0, or one far-first worker in this many
 };
 
 // Progress of the chain of tasks that rewrite the triangle R_kk (GEQRT(k),
@@ -1069,7 +1082,10 @@ struct TileKernels {
     // reflectors of a diagonal tile (Vd: V_kk as a dense unit-lower matrix,
     // T_kk): C <- Q_kk^T C (trans) or Q_kk C.
     template <bool TRANS>
-    __device__ __forceinline__ static void larfb(const double *Vd, const double *Tkk, double *Cb, int cbeg, int cend, double *smem) {
+    // With pp.prev (forward order only) the reflectors are those of a GEQRT
+    // still running, followed block by block as apply_dbuf does.
+    __device__ __forceinline__ static void larfb(const double *Vd, const double *Tkk, double *Cb, int cbeg, int cend,
+                                                 double *smem, const Pipe &pp = Pipe{}) {
         double *Vl = smem, *Tl = smem + (size_t)LDV * IB;
         // every wave works on a valid strip (waves past the end repeat the last
         // one) so that the strip's registers have a single definition; only
@@ -1080,7 +1096,7 @@ struct TileKernels {
         Strip<B> C;
         strip_load<B>(C, Cb + (size_t)col0 * B, B);
         if constexpr (DBUF) {
-            apply_dbuf<TRANS, false>(C, nullptr, Vd, Tkk, col0, owner, smem);
+            apply_dbuf<TRANS, false>(C, nullptr, Vd, Tkk, col0, owner, smem, pp);
         } else {
 #pragma unroll 1
             for (int si = 0; si < NB; ++si) {
@@ -1169,13 +1185,13 @@ struct TileKernels {
 
     template <bool TRANS, bool BF16 = false>
     __device__ __forceinline__ static void larfb_f32(const double *Vd, const double *Tkk, double *Cb, int cbeg, int cend,
-                                                     double *smem) {
+                                                     double *smem, const Pipe &pp = Pipe{}) {
         const int want = cbeg + 16 * wave_id();
         const int col0 = min(want, cend - 16);
         const bool owner = want < cend;
         StripF<B> C;
         strip_load_f<B>(C, Cb + (size_t)col0 * B, B);
-        apply_dbuf_f32<TRANS, false, BF16>(C, nullptr, Vd, Tkk, col0, owner, smem);
+        apply_dbuf_f32<TRANS, false, BF16>(C, nullptr, Vd, Tkk, col0, owner, smem, pp);
         if (owner) strip_store_f<B>(C, Cb + (size_t)col0 * B, B);
     }
 
@@ -1231,7 +1247,9 @@ struct FactorBody {
                     pp.prev_claim = claim + t.i - 1;
                 }
             } else if (t.kind == GEQRT) {
-                if (t.i + 1 < p) pp.mine = prog + row + t.i;
+                pp.mine = prog + row + t.i;  // read by TSQRT(k+1,k) and LARFB(k,k+1,c)
+            } else if (t.kind == LARFB && t.j == t.k + 1) {
+                pp.prev = prog + row + t.k;  // the V and T panels GEQRT(k) has stored
             } else if (t.kind == SSRFB && t.j == t.k + 1) {
                 pp.prev = panels + t.i;  // the panels of the TSQRT(i,k) whose reflectors it applies
             }
@@ -1251,9 +1269,9 @@ struct FactorBody {
             break;
         case LARFB:
             if constexpr (F32)
-                K::template larfb_f32<true, BF>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem);
+                K::template larfb_f32<true, BF>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem, pipe(t));
             else
-                K::template larfb<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem);
+                K::template larfb<true>(vdiag(t.k), tslot(t.k, t.k), tile(t.k, t.j), cbeg, cend, smem, pipe(t));
             break;
         default:
             if constexpr (F32)
@@ -1368,16 +1386,17 @@ struct TrsmBody {
 // ===========================================================================
 // Successors a task releases when it starts rather than when it ends (they
 // follow its progress word inside their bodies): with the pipelined chain,
-// TSQRT(i+1,k) after GEQRT(k) (i = k) or TSQRT(i,k), and the strips of
-// SSRFB(i,k+1,k) after TSQRT(i,k).  They are the first successors in the
-// graph's order; returns how many.
+// TSQRT(i+1,k) after GEQRT(k) (i = k) or TSQRT(i,k), the strips of
+// LARFB(k,k+1) after GEQRT(k), and the strips of SSRFB(i,k+1,k) after
+// TSQRT(i,k).  They are the first successors in the graph's order; returns
+// how many.
 template <class G, class Body>
 __device__ __forceinline__ int early_successors(const G &, const Body &, const Task &) { return 0; }
 template <int B, int IB, bool F32, bool BF>
 __device__ __forceinline__ int early_successors(const FactorGraph &g, const FactorBody<B, IB, F32, BF> &b, const Task &t) {
     if (!b.prog || (t.kind != GEQRT && t.kind != TSQRT)) return 0;
     const int chain = t.i + 1 < g.p ? 1 : 0;
-    if (t.kind == GEQRT) return chain;
+    if (t.kind == GEQRT) return chain + (t.k + 1 < g.q ? (int)g.S : 0);
     if (t.kind != TSQRT) return 0;
     return (g.helpers ? 1 : 0) + chain + (t.k + 1 < g.q ? (int)g.S : 0);
 }
@@ -1404,7 +1423,8 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
         if (tid == 0) {
             s_cont = next >= 0;
             s_task = next >= 0 ? next
-                               : idle_wait(g, o.policy, s, nsinks, o.abort_flag, rt_clock() + (uint64_t)o.timeout,
+                               : idle_wait(g, o.policy, o.far_every, s, nsinks, o.abort_flag,
+                                           rt_clock() + (uint64_t)o.timeout,
                                            blockIdx.x, nworkers);
             s_nready = 0;
             s_nover = 0;
@@ -1700,6 +1720,13 @@ std::vector<int64_t> serial_order(const ApplyGraph &g);
 std::vector<int64_t> serial_order(const TrsmGraph &g);
 template <class G>
 int64_t trace_count(const G &g) { return g.num_tasks(); }
+// far-first workers: the square or wide factorisation under the column policy
+template <class G>
+int far_every_of(const G &, int) { return 0; }
+template <>
+inline int far_every_of<FactorGraph>(const FactorGraph &g, int policy) {
+    return policy == TQR_POLICY_COLUMN && g.p <= g.q ? kFarEverySquare : 0;
+}
 template <>
 inline int64_t trace_count<FactorGraph>(const FactorGraph &g) { return g.num_paper_tasks(); }
 
@@ -1750,6 +1777,7 @@ tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, 
     ro.abort_flag = opt ? opt->abort_flag : nullptr;
     ro.timeout = (opt && opt->timeout_ticks > 0) ? opt->timeout_ticks : default_timeout_ticks();
     ro.policy = policy;
+    ro.far_every = far_every_of(g, policy);
     if (opt && opt->event_begin) HIPCHK(hipEventRecord((hipEvent_t)opt->event_begin, stream));
     hipLaunchKernelGGL(kp, dim3((unsigned)workers), dim3(NT), lds, stream, g, body, s, ro);
     HIPCHK(hipGetLastError());

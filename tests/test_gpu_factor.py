@@ -132,9 +132,11 @@ def test_schedules_are_bitwise_identical():
 def is_chain_edge(tu, tv):
     """Edges whose successor follows its predecessor's progress (task tuples
     are (kind, i, j, k, c)): GEQRT(k) -> TSQRT(k+1,k) and TSQRT(i,k) ->
-    TSQRT(i+1,k) on the chain that rewrites R_kk, and TSQRT(i,k) ->
-    SSRFB(i,k+1,k) (the next column's update)."""
+    TSQRT(i+1,k) on the chain that rewrites R_kk, GEQRT(k) -> LARFB(k,k+1,c)
+    and TSQRT(i,k) -> SSRFB(i,k+1,k) (the next column's update)."""
     if tu[0] in (0, 1) and tv[0] == 1 and tu[3] == tv[3] and tv[1] == tu[1] + 1:
+        return True
+    if tu[0] == 0 and tv[0] == 2 and tv[3] == tu[3] and tv[2] == tu[3] + 1:
         return True
     return tu[0] == 1 and tv[0] == 3 and tv[1] == tu[1] and tv[3] == tu[3] and tv[2] == tu[3] + 1
 
@@ -159,7 +161,7 @@ def test_trace_respects_the_task_graph():
         for v in tqr.graph_successors(p, q, b, u):
             tv = tqr.graph_task(p, q, b, v)
             if is_chain_edge(tu, tv):
-                # the pipelined R_kk chain: TSQRT(i+1,k) may start once its
+                # a pipelined edge: the successor may start once its
                 # predecessor has started and follows its progress inside
                 assert start[v] >= start[u], (tu, tv)
                 overlapped += int(start[v] < end[u])
