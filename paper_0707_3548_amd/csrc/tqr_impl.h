@@ -1390,10 +1390,14 @@ struct TrsmBody {
 // LARFB(k,k+1) after GEQRT(k), and the strips of SSRFB(i,k+1,k) after
 // TSQRT(i,k).  They are the first successors in the graph's order; returns
 // how many.
+// Early successors of one task, at most: a helper, the chain successor and
+// one per strip (at most 4 strips per tile).
+constexpr int kMaxEarly = 6;
 template <class G, class Body>
 __device__ __forceinline__ int early_successors(const G &, const Body &, const Task &) { return 0; }
 template <int B, int IB, bool F32, bool BF>
 __device__ __forceinline__ int early_successors(const FactorGraph &g, const FactorBody<B, IB, F32, BF> &b, const Task &t) {
+    static_assert((B > kStripCols ? B / kStripCols : 1) + 2 <= kMaxEarly, "more early successors than kMaxEarly");
     if (!b.prog || (t.kind != GEQRT && t.kind != TSQRT)) return 0;
     const int chain = t.i + 1 < g.p ? 1 : 0;
     if (t.kind == GEQRT) return chain + (t.k + 1 < g.q ? (int)g.S : 0);
@@ -1402,6 +1406,8 @@ __device__ __forceinline__ int early_successors(const FactorGraph &g, const Fact
 }
 
 constexpr int kReadyCap = 64;  // ready successors collected per task before publishing
+constexpr int kEarlyThread = 128;  // thread 0 of wavefront 2 releases the early successors
+static_assert(kEarlyThread < NT, "the releasing thread must exist");
 
 template <class G, class Body>
 __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunOpts o) {
@@ -1444,17 +1450,28 @@ __global__ void __launch_bounds__(NT) k_persistent(G g, Body body, Sched s, RunO
             if (task.kind == GEQRT && tid == 0)
                 __hip_atomic_store(&s.st->panel, task.k + 1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE);
         }
-        // successors that follow this task's progress may start as soon as
-        // it has started
+        // Successors that follow this task's progress may start as soon as
+        // it has started.  Thread 0 of wavefront 2 releases them while the
+        // body begins: the bodies that have such successors (GEQRT, TSQRT)
+        // start with wavefront 0 alone on its first panel, so the memory
+        // round trips of the release are off their critical path.  The
+        // counter decrements are issued together, then the pushes.
         const int nearly = early_successors(g, body, task);
-        if (nearly > 0 && tid == 0) {
+        if (nearly > 0 && tid == kEarlyThread) {
+            const int panel = flag_load(&s.st->panel);
+            int32_t old[kMaxEarly];
+#pragma unroll
+            for (int n = 0; n < kMaxEarly; ++n)
+                old[n] = n < nearly ? __hip_atomic_fetch_add(&s.cnt[g.successor(task, n)], -1, __ATOMIC_RELAXED,
+                                                             TQR_FLAG_SCOPE)
+                                    : 0;
             int pushed = 0;
-            for (int n = 0; n < nearly; ++n) {
+#pragma unroll
+            for (int n = 0; n < kMaxEarly; ++n) {
+                if (old[n] != 1) continue;
                 const int64_t e = g.successor(task, n);
-                if (__hip_atomic_fetch_add(&s.cnt[e], -1, __ATOMIC_RELAXED, TQR_FLAG_SCOPE) == 1) {
-                    push_one(s, level_of(g, g.decode(e), o.policy, flag_load(&s.st->panel)), (int32_t)e);
-                    ++pushed;
-                }
+                push_one(s, level_of(g, g.decode(e), o.policy, panel), (int32_t)e);
+                ++pushed;
             }
             if (pushed > 0) wake_idle(s, pushed, nworkers);
         }
