@@ -160,23 +160,31 @@ def cpu_baseline(A_host, seconds):
     m = A_host.shape[0]
     threads = oracle.num_threads(omp=True)
 
-    def run(cols):
+    def run(cols, omp=True):
         sample = np.asfortranarray(A_host[:, :cols])
         t0 = time.perf_counter()
-        oracle.geqr2(sample, omp=True)
+        oracle.geqr2(sample, omp=omp)
         return time.perf_counter() - t0
 
     def std(cols):
         return 2.0 * cols * cols * (m - cols / 3.0)
 
-    rate = std(512) / run(512)
-    cols = 512
-    while cols * 2 <= A_host.shape[1] and std(cols * 2) / rate <= seconds:
-        cols *= 2
-    dt = run(cols)
+    def widest(first, budget, omp):
+        rate = std(first) / run(first, omp)
+        cols = first
+        while cols * 2 <= A_host.shape[1] and std(cols * 2) / rate <= budget:
+            cols *= 2
+        return cols, run(cols, omp)
+
+    cols, dt = widest(512, seconds, True)
+    # the single-threaded build of the same oracle, on a sample half as long
+    cols1, dt1 = widest(128, seconds / 2, False)
     return {"value": round(std(cols) / dt / 1e9, 3), "unit": "Gflop/s", "cores": threads, "kind": "oracle",
             "sample": f"unblocked Householder QR (OpenMP over the trailing columns) of the leading {m}x{cols} "
-                      f"columns of the same 8192x8192 input, standard count 2n^2(m-n/3); {dt:.1f} s"}
+                      f"columns of the same 8192x8192 input, standard count 2n^2(m-n/3); {dt:.1f} s",
+            "single_thread": {"value": round(std(cols1) / dt1 / 1e9, 3), "unit": "Gflop/s", "cores": 1,
+                              "sample": f"the same oracle built without OpenMP, leading {m}x{cols1} columns; "
+                                        f"{dt1:.1f} s"}}
 
 
 def serving_leg(count: int, pool_size: int = 96):
