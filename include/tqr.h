@@ -115,7 +115,8 @@ typedef struct tqr_options {
 #define TQR_POLICY_LOOKAHEAD 1 /* as PAPER, but updates of the next panel's tile column first */
 #define TQR_POLICY_COLUMN 2    /* GEQRT > TSQRT > LARFB/SSRFB ordered by the distance of their tile
                                   column from the next panel (the later of step k+1 and the GEQRT
-                                  started last; nearer first, six levels) */
+                                  started last; nearer first, six levels); on grids at least as
+                                  wide as tall, one worker in four takes the farthest first */
 #define TQR_PRECISION_FP64 0         /* every kernel in FP64 */
 #define TQR_PRECISION_FP32_UPDATES 1 /* LARFB and SSRFB (the trailing updates, nearly all the
                                         flops) on the FP32 matrix cores; GEQRT/TSQRT (norms,

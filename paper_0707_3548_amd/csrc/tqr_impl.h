@@ -1080,10 +1080,10 @@ struct TileKernels {
 
     // DLARFB (LARFB) on columns [cbeg, cend) of a b-row tile with the
     // reflectors of a diagonal tile (Vd: V_kk as a dense unit-lower matrix,
-    // T_kk): C <- Q_kk^T C (trans) or Q_kk C.
+    // T_kk): C <- Q_kk^T C (trans) or Q_kk C.  With pp.prev (forward order
+    // only) the reflectors are those of a GEQRT still running, followed
+    // block by block as apply_dbuf does.
     template <bool TRANS>
-    // With pp.prev (forward order only) the reflectors are those of a GEQRT
-    // still running, followed block by block as apply_dbuf does.
     __device__ __forceinline__ static void larfb(const double *Vd, const double *Tkk, double *Cb, int cbeg, int cend,
                                                  double *smem, const Pipe &pp = Pipe{}) {
         double *Vl = smem, *Tl = smem + (size_t)LDV * IB;
@@ -1737,6 +1737,8 @@ std::vector<int64_t> serial_order(const ApplyGraph &g);
 std::vector<int64_t> serial_order(const TrsmGraph &g);
 template <class G>
 int64_t trace_count(const G &g) { return g.num_tasks(); }
+template <>
+inline int64_t trace_count<FactorGraph>(const FactorGraph &g) { return g.num_paper_tasks(); }
 // far-first workers: the square or wide factorisation under the column policy
 template <class G>
 int far_every_of(const G &, int) { return 0; }
@@ -1744,8 +1746,6 @@ template <>
 inline int far_every_of<FactorGraph>(const FactorGraph &g, int policy) {
     return policy == TQR_POLICY_COLUMN && g.p <= g.q ? kFarEverySquare : 0;
 }
-template <>
-inline int64_t trace_count<FactorGraph>(const FactorGraph &g) { return g.num_paper_tasks(); }
 
 template <class G, class Body>
 tqr_status run_graph(const G &g, const Body &body, void *sched_mem, size_t lds, const tqr_options *opt,
